@@ -1,0 +1,197 @@
+"""Benchmark of the simulator's hot path on one MI355X.
+
+Workload (synthetic, seeded): 30 qubits in complex128 (16 GiB state), 40
+layers; each layer applies a Haar-random U(2) to every qubit, then CNOT on a
+random perfect matching, with CZ instead of CNOT on every third layer (1800
+gates).  One step = the whole path on that circuit: state preparation, the
+compiler (DAG + permutation pass + lowering), every tile pass / data movement
+on the device, and read-out of <Z_q> for all q plus 1024 sampled amplitudes.
+
+Metric: amplitude-updates/s = gates x 2^n / step time (whole-job, inputs
+resident in HBM).  The pass form is the reported value; the plain gate-by-gate
+form is timed beside it.  The dominant kernel (the fused tile pass) is timed
+with HIP events around each launch on its own stream and priced against HBM.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--layers", type=int, default=40)
+    ap.add_argument("--dtype", default="c128")
+    ap.add_argument("--k", type=int, default=12)
+    ap.add_argument("--r", type=int, default=8)
+    ap.add_argument("--perm-exec", default="relabel")
+    ap.add_argument("--pinned", type=int, default=3)
+    ap.add_argument("--reg-bits", type=int, default=0)
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "tile_pass_traffic.json"))
+    return ap.parse_args()
+
+
+def cpu_baseline(gates, n, seconds):
+    """The oracle (plain C, complex128, OpenMP) on this host: gates of the
+    same circuit applied one by one until ``seconds`` have elapsed."""
+    import numpy as np
+
+    import oracle as O
+
+    O.lib()
+    s = O.zero_state(n)
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(gates) and time.perf_counter() - t0 < seconds:
+        g = gates[done]
+        q1 = int(g["q1"])
+        O.apply_gate(s, n, int(g["kind"]), int(g["q0"]), q1, g["u"])
+        done += 1
+    dt = time.perf_counter() - t0
+    del s
+    return dict(value=done * float(1 << n) / dt, unit="amplitude-updates/s", cores=O.threads(), kind="oracle",
+                sample=f"first {done} gates of the same {n}-qubit circuit, complex128, {dt:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_09746_amd import qsim as Q
+    from workloads import config_samples, layered_circuit, MASTER_SEED
+
+    n, dt = a.n, a.dtype
+    gates = layered_circuit(n, a.layers, MASTER_SEED + 2, cz_every_third=True)
+    samples = config_samples(2, n=n)
+    amp_updates = len(gates) * float(1 << n)
+    dev = Q.qs_device_info()
+    torch.cuda.init()
+    st = Q.State(n, dt)
+    stream = torch.cuda.current_stream()
+
+    pass_opts = dict(form="pass", k_tile=a.k, max_swaps=a.r, perm_exec=a.perm_exec, pinned=a.pinned,
+                     reg_bits=a.reg_bits)
+
+    def step(opts):
+        st.set_basis(0)
+        st.run(gates, **opts)
+        z = st.expect_z()
+        amp = st.amplitudes(samples)
+        return z, amp
+
+    def timed(opts, warmup, steps):
+        for _ in range(warmup):
+            step(opts)
+        torch.cuda.synchronize()
+        Q.qs_profile_read()  # drop warm-up records
+        Q.qs_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = step(opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Q.qs_profile_enable(False)
+        prof = Q.qs_profile_read()
+        return el / steps, prof, out
+
+    prog = Q.Program(gates, n, dt, **pass_opts)
+    pstats = prog.stats()
+    prog.close()
+
+    ms_pass, prof_pass, (z_pass, amp_pass) = timed(pass_opts, a.warmup, a.steps)
+    print(f"pass form: {ms_pass * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+
+    plain = None
+    if a.plain_steps > 0:
+        ms_plain, prof_plain, (z_plain, amp_plain) = timed(dict(form="plain"), 0, a.plain_steps)
+        agree = float(np.abs(amp_plain - amp_pass).max())
+        plain = dict(value=amp_updates / ms_plain, ms_per_step=ms_plain * 1e3,
+                     max_abs_diff_vs_pass=agree,
+                     kernels={k: dict(launches=v["launches"], avg_ms=v["avg_ms"],
+                                      achieved_gbs=v["bytes"] / (v["total_ms"] * 1e-3) / 1e9)
+                              for k, v in prof_plain.items()})
+        print(f"plain form: {ms_plain * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+
+    tile = prof_pass.get("tile_pass")
+    roofline = None
+    if tile:
+        per_launch = tile["bytes"] / tile["launches"]
+        achieved = per_launch / (tile["avg_ms"] * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(a.traffic_json):
+            try:
+                tj = json.load(open(a.traffic_json))
+                key = f"n{n}_{dt}_k{a.k}_r{a.r}_{a.perm_exec}"
+                traffic = tj.get(key)
+            except Exception:
+                traffic = None
+        roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                        traffic=traffic, kernel="k_tile", algorithmic_bytes_per_launch=per_launch,
+                        avg_ms=tile["avg_ms"], launches_per_step=tile["launches"] / a.steps)
+
+    cpu = None
+    if a.cpu_seconds > 0:
+        torch.cuda.synchronize()
+        st.close()
+        del st
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(gates, n, a.cpu_seconds)
+
+    value = amp_updates / ms_pass
+    line = {
+        "metric": "amplitude-updates/s",
+        "value": value,
+        "unit": "amplitude-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_pass * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dt == "c128" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"random circuit, n={n} {dt}, {a.layers} layers of Haar U(2) on every qubit + CNOT on a "
+                        f"random perfect matching (CZ every third layer), {len(gates)} gates; read-out <Z_q> all q "
+                        f"+ {len(samples)} sampled amplitudes",
+            "form": f"permutation pass k={a.k} r={a.r} pinned={a.pinned} perm_exec={a.perm_exec}",
+            "parallelism": "1 GPU",
+        },
+        "pass_stats": {k: pstats[k] for k in ("n_perm", "n_swaps", "n_tile_passes", "n_move_passes", "n_remaps",
+                                              "compile_ms")},
+        "kernels": {k: dict(launches=v["launches"], avg_ms=v["avg_ms"],
+                            achieved_gbs=v["bytes"] / max(v["total_ms"], 1e-9) / 1e6)
+                    for k, v in prof_pass.items()},
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": dev,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

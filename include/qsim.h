@@ -1,0 +1,222 @@
+/*
+ * qsim.h: C boundary of the MI355X state-vector simulator.
+ *
+ * The operations follow the problem statement of Guerreschi, "Fast simulation
+ * of quantum algorithms using circuit optimization" (arXiv:2010.09746):
+ *   - a state of n qubits is the vector of its 2^n complex amplitudes
+ *     (Section 2);
+ *   - qubit q is bit q of the logical basis index, i = sum_q i_q 2^q, and under
+ *     a qubit placement sigma the amplitude a_i is stored at physical index
+ *     j(i, sigma) = sum_q i_q 2^sigma(q) (Section 2);
+ *   - gates are one-qubit gates and controlled one-qubit gates, which update
+ *     amplitudes in pairs (Section 2);
+ *   - PermuteQubits(sigma') re-orders the stored amplitudes to a new placement
+ *     (Section 2, Appendix A);
+ *   - a compiled circuit is a list of ApplyGate and PermuteQubits
+ *     instructions produced by the pass of Section 3 (Algorithm 1).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a qs_status; no C++ exception crosses this boundary.
+ *     On failure qs_last_error() returns a message for the calling thread.
+ *   - "device" pointers are HIP device addresses on the current device;
+ *     "host" pointers are ordinary CPU memory owned by the caller.
+ *   - Calls that apply gates or move data are enqueued on the state's HIP
+ *     stream and return before the work finishes.  Read-out calls wait for
+ *     the state's stream and fill caller-owned host arrays.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - The library never frees memory it did not allocate.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qs_state qs_state;
+typedef struct qs_program qs_program;
+typedef struct qs_batch qs_batch;
+
+typedef enum {
+    QS_C64 = 0,  /* complex64: float re, im (8 bytes per amplitude)  */
+    QS_C128 = 1  /* complex128: double re, im (16 bytes per amplitude) */
+} qs_dtype;
+
+typedef enum {
+    QS_OK = 0,
+    QS_ERR_ARG = -1,         /* invalid argument (qubit range, sigma not a permutation, sizes) */
+    QS_ERR_OOM = -2,         /* device allocation failed */
+    QS_ERR_BUDGET = -3,      /* a request does not fit the memory budget */
+    QS_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+    QS_ERR_UNSUPPORTED = -5, /* valid request outside what this build implements */
+    QS_ERR_STATE = -6        /* handle in the wrong state (e.g. program compiled for another placement) */
+} qs_status;
+
+/* Gate kinds (paper, Section 2: one-qubit gates and controlled one-qubit gates). */
+typedef enum {
+    QS_GATE_U = 0,  /* 2x2 matrix u on qubit q0 */
+    QS_GATE_CX = 1, /* controlled X: control q0, target q1 (u ignored) */
+    QS_GATE_CZ = 2, /* controlled Z on q0, q1 (symmetric; u ignored) */
+    QS_GATE_CU = 3  /* controlled u: control q0, target q1 */
+} qs_gate_kind;
+
+/* One gate, 80 bytes.  u holds the 2x2 matrix row-major as interleaved
+ * (re, im): u00, u01, u10, u11.  Qubits are logical indices in [0, n). */
+typedef struct {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1; /* -1 for one-qubit gates */
+    int32_t reserved;
+    double u[8];
+} qs_gate;
+
+enum { QS_FORM_PLAIN = 0, QS_FORM_PASS = 1 };
+enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
+
+/* Options of qs_compile / qs_run_circuit.
+ *   form       QS_FORM_PLAIN: one kernel launch per gate.
+ *              QS_FORM_PASS: the pass of Section 3 with m = k_tile local
+ *              (in-tile) qubits; each run of local gates becomes one fused tile
+ *              pass over HBM.
+ *   k_tile     tile qubits (7..14, at most n).  A tile is 2^k_tile amplitudes
+ *              held by one workgroup.
+ *   max_swaps  r >= 1: local/global exchanges chained into one PermuteQubits.
+ *              r = 1 with pinned = 0 is Algorithm 1 as printed.
+ *   pinned     qubits at positions < pinned are never exchanged out.
+ *   perm_exec  QS_PERM_MOVE: each PermuteQubits moves the amplitudes (in place)
+ *              and tiles are contiguous.  QS_PERM_RELABEL: no data moves; each
+ *              tile pass gathers the positions of the current local qubits.
+ *   max_fuse   upper bound on gates per tile pass (0 = none).
+ *   reg_bits   amplitudes per thread = 2^reg_bits inside the tile kernel
+ *              (0 = chosen by the library).
+ */
+typedef struct {
+    int32_t form;
+    int32_t k_tile;
+    int32_t max_swaps;
+    int32_t pinned;
+    int32_t perm_exec;
+    int32_t max_fuse;
+    int32_t reg_bits;
+    int32_t reserved;
+} qs_run_opts;
+
+typedef struct {
+    int64_t n_gates;        /* gates in the circuit */
+    int64_t n_apply;        /* ApplyGate instructions on local qubits */
+    int64_t n_perm;         /* PermuteQubits instructions */
+    int64_t n_global;       /* gates applied while not local (Algorithm 1 fallback) */
+    int64_t n_swaps;        /* local/global exchanges summed over all PermuteQubits */
+    int64_t n_tile_passes;  /* fused tile kernel launches */
+    int64_t n_move_passes;  /* data-movement launches for PermuteQubits */
+    int64_t n_plain;        /* one-gate kernel launches */
+    int64_t n_remaps;       /* register/LDS re-layouts inside all tile passes */
+    double compile_ms;      /* host time of qs_compile */
+} qs_program_stats;
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *qs_last_error(void);
+
+/* Properties of the current HIP device.  name: host buffer of name_len bytes. */
+qs_status qs_device_info(int *cu_count, int *lds_bytes_per_cu, size_t *hbm_bytes, char *name,
+                         int name_len);
+
+/* ---- state ------------------------------------------------------------- */
+
+/* Create an n-qubit state (1 <= n <= 34) of type dt on the current device.
+ * device_buf: caller-owned device buffer of at least 2^n * (8 or 16) bytes
+ *   (buf_bytes), e.g. a torch tensor; NULL lets the library allocate (and
+ *   later free) it.  stream: hipStream_t for all work on this state (NULL =
+ *   the default stream).  The amplitudes are set to |0...0> with the identity
+ *   placement.  Also allocates a small read-out workspace. */
+qs_status qs_state_create(int n, qs_dtype dt, void *device_buf, size_t buf_bytes, void *stream,
+                          qs_state **out);
+qs_status qs_state_destroy(qs_state *s);
+qs_status qs_state_set_stream(qs_state *s, void *stream);
+/* n, dtype, device buffer of the state (any pointer may be NULL). */
+qs_status qs_state_info(const qs_state *s, int *n, int *dtype, void **device_buf);
+
+/* State preparation (Section 2): |x> for logical index x, identity placement. */
+qs_status qs_state_set_basis(qs_state *s, uint64_t logical_index);
+
+/* Current placement: sigma[q] = position of qubit q (host array of n ints). */
+qs_status qs_get_permutation(const qs_state *s, int *sigma);
+
+/* ---- gates and data movement -------------------------------------------- */
+
+/* Apply one gate (logical qubits, mapped through the placement) as one
+ * kernel launch: the plain gate-by-gate form. */
+qs_status qs_apply_gate(qs_state *s, const qs_gate *g);
+qs_status qs_apply_gates(qs_state *s, const qs_gate *g, int64_t n_gates);
+
+/* PermuteQubits(sigma_new) (Section 2, Appendix A): move every amplitude from
+ * j(i, sigma) to j(i, sigma_new) in place.  sigma_new: host array of n ints,
+ * a permutation of 0..n-1.  Bit-exact data movement. */
+qs_status qs_permute_qubits(qs_state *s, const int *sigma_new);
+
+/* ---- compiled circuits (Section 3, Algorithm 1) ------------------------- */
+
+/* Compile n_gates gates (host array) for n qubits and amplitude type dt.
+ * sigma0: host array of the placement the program will start from (NULL =
+ * identity).  Host-only; device tables are uploaded on first run. */
+qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt,
+                     const int *sigma0, const qs_run_opts *opts, qs_program **out);
+qs_status qs_program_destroy(qs_program *p);
+qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
+/* Instruction list of the pass as int32 words: 0 v = ApplyGate(v) local;
+ * 1 s_0..s_{n-1} = PermuteQubits(s); 2 v = ApplyGate(v) not local.
+ * Writes up to cap words into buf (host) and the full length into *len. */
+qs_status qs_program_instructions(const qs_program *p, int32_t *buf, int64_t cap, int64_t *len);
+
+/* Enqueue a compiled program on the state's stream.  The state's placement
+ * must equal the program's sigma0; afterwards it is the program's final one. */
+qs_status qs_run_program(qs_state *s, const qs_program *p);
+/* Compile with the state's placement, run, destroy the program. */
+qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates,
+                         const qs_run_opts *opts);
+
+/* ---- read-out (FP64 accumulation) --------------------------------------- */
+
+/* Amplitudes at count logical indices (host array) into out (host, 2*count
+ * doubles, interleaved re, im). */
+qs_status qs_read_amplitudes(qs_state *s, const uint64_t *logical_idx, int64_t count, double *out);
+/* All 2^n amplitudes in logical order into out (host, 2^(n+1) doubles). */
+qs_status qs_read_state(qs_state *s, double *out);
+/* <Z_q> = sum_i |a_i|^2 (1 - 2 i_q) for q = 0..n-1 into out (host, n doubles). */
+qs_status qs_expect_z(qs_state *s, double *out);
+/* sum_i |a_i|^2 into *out. */
+qs_status qs_norm(qs_state *s, double *out);
+/* Both states must have the same n.  loss = 1 - |<a|b>|^2 / (<a|a><b|b>),
+ * max_abs_diff = max_i |a_i - b_i| over logical indices, all in FP64. */
+qs_status qs_fidelity(qs_state *a, qs_state *b, double *loss, double *max_abs_diff);
+/* Wait for all work enqueued on the state's stream. */
+qs_status qs_synchronize(qs_state *s);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Per kernel class: launches recorded, summed device time between HIP events
+ * recorded on the launching stream around each launch, and the algorithmic
+ * HBM bytes of those launches (every amplitude a launch must read and write,
+ * counted once). */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} qs_profile_entry;
+
+/* on != 0: record events around every subsequent launch (all states, this
+ * process); 0: stop recording. */
+qs_status qs_profile_enable(int on);
+/* Wait for the recorded events, write up to cap entries (host array) and the
+ * number of classes into *n_out, and clear the records. */
+qs_status qs_profile_read(qs_profile_entry *out, int cap, int *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM_H */

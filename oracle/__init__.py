@@ -70,6 +70,7 @@ def lib():
         L.orc_gate_is_local.restype = ctypes.c_int
         L.orc_commute.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_commute.restype = ctypes.c_int
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -111,6 +112,11 @@ def run(gates: np.ndarray, n: int, x: int = 0, state: np.ndarray | None = None) 
     rc = lib().orc_run(_d(s.view(np.float64)), n, g.ctypes.data, len(g))
     assert rc == 0
     return s
+
+
+def threads() -> int:
+    """OpenMP threads used by the simulator loops."""
+    return int(lib().orc_threads())
 
 
 def norm(state: np.ndarray, n: int) -> float:

@@ -19,6 +19,7 @@
  *   CZ(a, b):  a_i <- -a_i where bits a and b are both 1
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -174,4 +175,10 @@ void orc_permute(const double *src, double *dst, int n, const int *sigma_from, c
         dst[2 * b] = src[2 * a];
         dst[2 * b + 1] = src[2 * a + 1];
     }
+}
+
+/* OpenMP threads the loops above run with. */
+int orc_threads(void)
+{
+    return omp_get_max_threads();
 }

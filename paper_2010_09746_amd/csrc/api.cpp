@@ -1,0 +1,731 @@
+// C boundary (include/qsim.h): state handles, the program executor and the
+// read-out glue.  Every entry point converts internal errors into a status
+// code and a per-thread message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace qsim;
+
+struct qs_state {
+    int n = 0;
+    qs_dtype dt = QS_C128;
+    void *buf = nullptr;
+    bool owns = false;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    int dev = 0;
+    std::vector<int> sigma;
+    double *d_work = nullptr;      // read-out partials and results
+    size_t work_doubles = 0;
+    uint64_t *d_idx = nullptr;     // gather indices
+    double *d_amp = nullptr;       // gathered amplitudes
+    int64_t idx_cap = 0;
+};
+
+struct qs_program {
+    Program p;
+};
+
+namespace qsim {
+
+[[noreturn]] void fail(qs_status code, const std::string &msg) { throw Error{code, msg}; }
+
+}  // namespace qsim
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F> qs_status guard(F &&f)
+{
+    try {
+        f();
+        g_err.clear();
+        return QS_OK;
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return QS_ERR_OOM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return QS_ERR_ARG;
+    } catch (...) {
+        g_err = "unknown error";
+        return QS_ERR_ARG;
+    }
+}
+
+void hipchk(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? QS_ERR_OOM : QS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+size_t elem_bytes(qs_dtype dt) { return dt == QS_C64 ? 8 : 16; }
+
+void need(bool cond, const char *msg)
+{
+    if (!cond)
+        fail(QS_ERR_ARG, msg);
+}
+
+// ---------------------------------------------------------------------------
+// launch profiling: HIP events recorded on the launching stream around each
+// launch, resolved when read
+
+enum ProfClass { P_TILE, P_U, P_CU, P_CX, P_CZ, P_MOVE, P_BASIS, P_ZSUM, P_GATHER, P_FID, P_NCLASS };
+const char *const PROF_NAMES[P_NCLASS] = {"tile_pass", "plain_u", "plain_cu", "plain_cx", "plain_cz",
+                                          "move_involution", "set_basis", "zsum", "gather", "fidelity"};
+
+struct ProfRec {
+    int cls;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pool_event()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess)
+        fail(QS_ERR_HIP, "hipEventCreate");
+    return e;
+}
+
+template <typename F> void timed(hipStream_t st, int cls, double bytes, F &&f)
+{
+    if (!g_prof_on) {
+        f();
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t a = pool_event(), b = pool_event();
+    if (hipEventRecord(a, st) != hipSuccess)
+        fail(QS_ERR_HIP, "hipEventRecord");
+    f();
+    if (hipEventRecord(b, st) != hipSuccess)
+        fail(QS_ERR_HIP, "hipEventRecord");
+    g_recs.push_back(ProfRec{cls, bytes, a, b});
+}
+
+int gate_class(int kind)
+{
+    switch (kind) {
+    case QS_GATE_U: return P_U;
+    case QS_GATE_CU: return P_CU;
+    case QS_GATE_CX: return P_CX;
+    default: return P_CZ;
+    }
+}
+
+// algorithmic bytes of one plain gate: every amplitude it must read and write
+double gate_bytes(int kind, int n, size_t eb)
+{
+    const double N = std::ldexp(1.0, n);
+    switch (kind) {
+    case QS_GATE_U: return 2 * N * eb;
+    case QS_GATE_CU:
+    case QS_GATE_CX: return N * eb;
+    default: return 0.5 * N * eb;
+    }
+}
+
+void check_perm(const int *sigma, int n)
+{
+    need(sigma != nullptr, "sigma is NULL");
+    std::vector<char> seen(n, 0);
+    for (int q = 0; q < n; ++q) {
+        need(sigma[q] >= 0 && sigma[q] < n && !seen[sigma[q]], "sigma is not a permutation of 0..n-1");
+        seen[sigma[q]] = 1;
+    }
+}
+
+void check_gate(const qs_gate &g, int n)
+{
+    need(g.kind >= QS_GATE_U && g.kind <= QS_GATE_CU, "unknown gate kind");
+    need(g.q0 >= 0 && g.q0 < n, "gate qubit out of range");
+    if (g.kind != QS_GATE_U)
+        need(g.q1 >= 0 && g.q1 < n && g.q1 != g.q0, "two-qubit gate needs two distinct qubits in range");
+}
+
+void ensure_work(qs_state *s, size_t doubles)
+{
+    if (s->work_doubles >= doubles)
+        return;
+    if (s->d_work)
+        hipchk(hipFree(s->d_work), "hipFree");
+    s->d_work = nullptr;
+    s->work_doubles = 0;
+    hipchk(hipMalloc(&s->d_work, doubles * sizeof(double)), "hipMalloc(read-out workspace)");
+    s->work_doubles = doubles;
+}
+
+void ensure_gather(qs_state *s, int64_t count)
+{
+    if (s->idx_cap >= count)
+        return;
+    if (s->d_idx)
+        hipchk(hipFree(s->d_idx), "hipFree");
+    if (s->d_amp)
+        hipchk(hipFree(s->d_amp), "hipFree");
+    s->d_idx = nullptr;
+    s->d_amp = nullptr;
+    s->idx_cap = 0;
+    hipchk(hipMalloc(&s->d_idx, count * sizeof(uint64_t)), "hipMalloc(gather)");
+    hipchk(hipMalloc(&s->d_amp, count * 2 * sizeof(double)), "hipMalloc(gather)");
+    s->idx_cap = count;
+}
+
+uint64_t phys_index(uint64_t i, const std::vector<int> &sigma)
+{
+    uint64_t j = 0;
+    for (size_t q = 0; q < sigma.size(); ++q)
+        if ((i >> q) & 1)
+            j |= 1ull << sigma[q];
+    return j;
+}
+
+// Apply the position map pi (amplitude at x moves to the index whose bit
+// pi[p] is bit p of x) as at most two in-place involutions: along each cycle
+// c_0 -> c_1 -> ... -> c_{L-1} of pi, first c_i -> c_{-i}, then c_i -> c_{1-i}
+// (indices mod L); the composition sends c_i to c_{i+1}.
+void apply_position_map(qs_state *s, const std::vector<int> &pi)
+{
+    const int n = s->n;
+    std::vector<int> r1(n), r2(n);
+    for (int p = 0; p < n; ++p)
+        r1[p] = r2[p] = p;
+    std::vector<char> seen(n, 0);
+    for (int p = 0; p < n; ++p) {
+        if (seen[p])
+            continue;
+        std::vector<int> cyc;
+        for (int x = p; !seen[x]; x = pi[x]) {
+            seen[x] = 1;
+            cyc.push_back(x);
+        }
+        const int L = (int)cyc.size();
+        for (int i = 0; i < L; ++i) {
+            r1[cyc[i]] = cyc[((-i) % L + L) % L];
+            r2[cyc[i]] = cyc[((1 - i) % L + L) % L];
+        }
+    }
+    for (const std::vector<int> *r : {&r1, &r2}) {
+        int pairs = 0;
+        for (int p = 0; p < n; ++p)
+            pairs += (*r)[p] > p;
+        if (pairs == 0)
+            continue;
+        const double bytes = 2.0 * (1.0 - std::ldexp(1.0, -pairs)) * std::ldexp(1.0, n) * elem_bytes(s->dt);
+        timed(s->stream, P_MOVE, bytes, [&] { launch_involution(s->buf, s->dt, n, *r, s->stream); });
+    }
+}
+
+void upload_ops(Program &p)
+{
+    int dev = 0;
+    hipchk(hipGetDevice(&dev), "hipGetDevice");
+    if (p.d_ops && p.dev == dev)
+        return;
+    if (p.ops.empty())
+        return;
+    if (p.d_ops) {
+        int cur = dev;
+        hipchk(hipSetDevice(p.dev), "hipSetDevice");
+        (void)hipFree(p.d_ops);
+        hipchk(hipSetDevice(cur), "hipSetDevice");
+        p.d_ops = nullptr;
+    }
+    hipchk(hipMalloc(&p.d_ops, p.ops.size() * sizeof(TileOp)), "hipMalloc(tile ops)");
+    hipchk(hipMemcpy(p.d_ops, p.ops.data(), p.ops.size() * sizeof(TileOp), hipMemcpyHostToDevice),
+           "hipMemcpy(tile ops)");
+    p.dev = dev;
+}
+
+void run_launches(qs_state *s, Program &p)
+{
+    need(s->n == p.n, "program compiled for a different qubit count");
+    need(s->dt == p.dt, "program compiled for a different amplitude type");
+    if (s->sigma != p.sigma0)
+        fail(QS_ERR_STATE, "state placement differs from the program's starting placement");
+    upload_ops(p);
+    for (const Launch &L : p.launches) {
+        switch (L.type) {
+        case L_PLAIN:
+            timed(s->stream, gate_class(L.gate.kind), gate_bytes(L.gate.kind, s->n, elem_bytes(s->dt)),
+                  [&] { launch_plain_gate(s->buf, s->dt, s->n, L.gate, s->stream); });
+            break;
+        case L_MOVE:
+            apply_position_map(s, L.pi);
+            break;
+        case L_TILE: {
+            TileArgs a{};
+            a.state = s->buf;
+            a.ops = p.d_ops + L.op_begin;
+            a.n_ops = L.op_count;
+            a.n_hi = s->n - L.k;
+            for (int b = 0; b < L.k; ++b)
+                a.pos[b] = (uint8_t)L.pos[b];
+            a.has_perm = 0;
+            const uint64_t tiles = 1ull << (s->n - L.k);
+            timed(s->stream, P_TILE, 2.0 * (double)s->bytes, [&] {
+                if (s->dt == QS_C64)
+                    launch_tile_f32(a, tiles, L.log_r, L.log_nt, s->stream);
+                else
+                    launch_tile_f64(a, tiles, L.log_r, L.log_nt, s->stream);
+            });
+            break;
+        }
+        }
+    }
+    s->sigma = p.sigma_final;
+}
+
+qs_run_opts default_opts()
+{
+    qs_run_opts o{};
+    o.form = QS_FORM_PASS;
+    o.k_tile = 12;
+    o.max_swaps = 1;
+    o.pinned = 0;
+    o.perm_exec = QS_PERM_MOVE;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qs_last_error(void) { return g_err.c_str(); }
+
+qs_status qs_device_info(int *cu_count, int *lds_bytes, size_t *hbm_bytes, char *name, int name_len)
+{
+    return guard([&] {
+        int dev = 0;
+        hipchk(hipGetDevice(&dev), "hipGetDevice");
+        hipDeviceProp_t prop;
+        hipchk(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        if (cu_count)
+            *cu_count = prop.multiProcessorCount;
+        if (lds_bytes)
+            *lds_bytes = (int)prop.maxSharedMemoryPerMultiProcessor;
+        if (hbm_bytes)
+            *hbm_bytes = prop.totalGlobalMem;
+        if (name && name_len > 0) {
+            std::string nm = std::string(prop.name) + " " + prop.gcnArchName;
+            std::strncpy(name, nm.c_str(), (size_t)name_len - 1);
+            name[name_len - 1] = 0;
+        }
+    });
+}
+
+qs_status qs_state_create(int n, qs_dtype dt, void *device_buf, size_t buf_bytes, void *stream, qs_state **out)
+{
+    return guard([&] {
+        need(out != nullptr, "out is NULL");
+        *out = nullptr;
+        need(n >= 1 && n <= MAX_QUBITS, "n must be in [1, 34]");
+        need(dt == QS_C64 || dt == QS_C128, "unknown dtype");
+        const size_t bytes = elem_bytes(dt) << n;
+        auto *s = new qs_state();
+        try {
+            s->n = n;
+            s->dt = dt;
+            s->stream = reinterpret_cast<hipStream_t>(stream);
+            hipchk(hipGetDevice(&s->dev), "hipGetDevice");
+            s->sigma.resize(n);
+            for (int q = 0; q < n; ++q)
+                s->sigma[q] = q;
+            if (device_buf) {
+                need(buf_bytes >= bytes, "device buffer smaller than 2^n amplitudes");
+                need(reinterpret_cast<uintptr_t>(device_buf) % 16 == 0, "device buffer must be 16-byte aligned");
+                s->buf = device_buf;
+                s->owns = false;
+            } else {
+                hipchk(hipMalloc(&s->buf, bytes), "hipMalloc(state)");
+                s->owns = true;
+            }
+            s->bytes = bytes;
+            launch_set_basis(s->buf, dt, n, 0, s->stream);
+        } catch (...) {
+            if (s->owns && s->buf)
+                (void)hipFree(s->buf);
+            delete s;
+            throw;
+        }
+        *out = s;
+    });
+}
+
+qs_status qs_state_destroy(qs_state *s)
+{
+    return guard([&] {
+        if (!s)
+            return;
+        (void)hipStreamSynchronize(s->stream);
+        if (s->owns && s->buf)
+            (void)hipFree(s->buf);
+        if (s->d_work)
+            (void)hipFree(s->d_work);
+        if (s->d_idx)
+            (void)hipFree(s->d_idx);
+        if (s->d_amp)
+            (void)hipFree(s->d_amp);
+        delete s;
+    });
+}
+
+qs_status qs_state_set_stream(qs_state *s, void *stream)
+{
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        s->stream = reinterpret_cast<hipStream_t>(stream);
+    });
+}
+
+qs_status qs_state_info(const qs_state *s, int *n, int *dtype, void **device_buf)
+{
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        if (n)
+            *n = s->n;
+        if (dtype)
+            *dtype = (int)s->dt;
+        if (device_buf)
+            *device_buf = s->buf;
+    });
+}
+
+qs_status qs_state_set_basis(qs_state *s, uint64_t x)
+{
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        need(s->n == 64 || x < (1ull << s->n), "basis index out of range");
+        for (int q = 0; q < s->n; ++q)
+            s->sigma[q] = q;
+        timed(s->stream, P_BASIS, (double)s->bytes, [&] { launch_set_basis(s->buf, s->dt, s->n, x, s->stream); });
+    });
+}
+
+qs_status qs_get_permutation(const qs_state *s, int *sigma)
+{
+    return guard([&] {
+        need(s != nullptr && sigma != nullptr, "NULL argument");
+        std::copy(s->sigma.begin(), s->sigma.end(), sigma);
+    });
+}
+
+qs_status qs_apply_gate(qs_state *s, const qs_gate *g) { return qs_apply_gates(s, g, 1); }
+
+qs_status qs_apply_gates(qs_state *s, const qs_gate *g, int64_t n_gates)
+{
+    return guard([&] {
+        need(s != nullptr && (g != nullptr || n_gates == 0), "NULL argument");
+        need(n_gates >= 0, "negative gate count");
+        for (int64_t i = 0; i < n_gates; ++i)
+            check_gate(g[i], s->n);
+        for (int64_t i = 0; i < n_gates; ++i) {
+            qs_gate p = g[i];
+            p.q0 = s->sigma[g[i].q0];
+            p.q1 = g[i].kind == QS_GATE_U ? -1 : s->sigma[g[i].q1];
+            timed(s->stream, gate_class(p.kind), gate_bytes(p.kind, s->n, elem_bytes(s->dt)),
+                  [&] { launch_plain_gate(s->buf, s->dt, s->n, p, s->stream); });
+        }
+    });
+}
+
+qs_status qs_permute_qubits(qs_state *s, const int *sigma_new)
+{
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        check_perm(sigma_new, s->n);
+        std::vector<int> pi(s->n);
+        for (int q = 0; q < s->n; ++q)
+            pi[s->sigma[q]] = sigma_new[q];
+        apply_position_map(s, pi);
+        s->sigma.assign(sigma_new, sigma_new + s->n);
+    });
+}
+
+qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
+                     const qs_run_opts *opts, qs_program **out)
+{
+    return guard([&] {
+        need(out != nullptr, "out is NULL");
+        *out = nullptr;
+        need(gates != nullptr || n_gates == 0, "gates is NULL");
+        need(n_gates >= 0 && n_gates < (1ll << 30), "gate count out of range");
+        need(n >= 1 && n <= MAX_COMPILE_QUBITS, "n must be in [1, 63]");
+        need(dt == QS_C64 || dt == QS_C128, "unknown dtype");
+        if (sigma0)
+            check_perm(sigma0, n);
+        for (int64_t i = 0; i < n_gates; ++i)
+            check_gate(gates[i], n);
+        qs_run_opts o = opts ? *opts : default_opts();
+        if (o.form == QS_FORM_PASS)
+            need(o.k_tile >= 1, "k_tile must be >= 1");
+        auto *p = new qs_program();
+        try {
+            compile_program(gates, n_gates, n, dt, sigma0, o, p->p);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+    });
+}
+
+qs_status qs_program_destroy(qs_program *p)
+{
+    return guard([&] {
+        if (!p)
+            return;
+        if (p->p.d_ops) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(p->p.dev);
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p->p.d_ops);
+            (void)hipSetDevice(cur);
+        }
+        delete p;
+    });
+}
+
+qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out)
+{
+    return guard([&] {
+        need(p != nullptr && out != nullptr, "NULL argument");
+        *out = p->p.stats;
+    });
+}
+
+qs_status qs_program_instructions(const qs_program *p, int32_t *buf, int64_t cap, int64_t *len)
+{
+    return guard([&] {
+        need(p != nullptr && len != nullptr, "NULL argument");
+        int64_t w = 0;
+        auto put = [&](int32_t x) {
+            if (buf && w < cap)
+                buf[w] = x;
+            ++w;
+        };
+        for (const Instr &I : p->p.instrs) {
+            put(I.type);
+            if (I.type == 1)
+                for (int x : I.sigma)
+                    put(x);
+            else
+                put(I.gate);
+        }
+        *len = w;
+    });
+}
+
+qs_status qs_run_program(qs_state *s, const qs_program *p)
+{
+    return guard([&] {
+        need(s != nullptr && p != nullptr, "NULL argument");
+        run_launches(s, const_cast<qs_program *>(p)->p);
+    });
+}
+
+qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts)
+{
+    qs_program *p = nullptr;
+    qs_status rc = QS_OK;
+    rc = qs_compile(gates, n_gates, s ? s->n : 0, s ? s->dt : QS_C128, s ? s->sigma.data() : nullptr, opts, &p);
+    if (rc != QS_OK)
+        return rc;
+    rc = qs_run_program(s, p);
+    std::string err = g_err;
+    // the program's device tables must outlive the enqueued work
+    (void)hipStreamSynchronize(s->stream);
+    qs_program_destroy(p);
+    g_err = err;
+    return rc;
+}
+
+qs_status qs_synchronize(qs_state *s)
+{
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    });
+}
+
+qs_status qs_read_amplitudes(qs_state *s, const uint64_t *idx, int64_t count, double *out)
+{
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        need(count >= 0 && (count == 0 || (idx && out)), "bad arguments");
+        if (count == 0)
+            return;
+        std::vector<uint64_t> phys(count);
+        for (int64_t i = 0; i < count; ++i) {
+            need(s->n == 64 || idx[i] < (1ull << s->n), "amplitude index out of range");
+            phys[i] = phys_index(idx[i], s->sigma);
+        }
+        ensure_gather(s, count);
+        hipchk(hipMemcpyAsync(s->d_idx, phys.data(), count * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream),
+               "hipMemcpyAsync");
+        timed(s->stream, P_GATHER, (double)count * elem_bytes(s->dt),
+              [&] { launch_gather(s->buf, s->dt, s->d_idx, count, s->d_amp, s->stream); });
+        hipchk(hipMemcpyAsync(out, s->d_amp, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+               "hipMemcpyAsync");
+        hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    });
+}
+
+qs_status qs_read_state(qs_state *s, double *out)
+{
+    return guard([&] {
+        need(s != nullptr && out != nullptr, "NULL argument");
+        need(s->n <= 30, "qs_read_state is limited to n <= 30");
+        const uint64_t N = 1ull << s->n;
+        std::vector<unsigned char> raw(s->bytes);
+        hipchk(hipMemcpyAsync(raw.data(), s->buf, s->bytes, hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+        hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        for (uint64_t i = 0; i < N; ++i) {
+            const uint64_t j = phys_index(i, s->sigma);
+            if (s->dt == QS_C64) {
+                const float *f = reinterpret_cast<const float *>(raw.data());
+                out[2 * i] = f[2 * j];
+                out[2 * i + 1] = f[2 * j + 1];
+            } else {
+                const double *d = reinterpret_cast<const double *>(raw.data());
+                out[2 * i] = d[2 * j];
+                out[2 * i + 1] = d[2 * j + 1];
+            }
+        }
+    });
+}
+
+static void zsum(qs_state *s, std::vector<double> &res)
+{
+    const size_t w = zsum_work_doubles(s->n) + (size_t)s->n + 1;
+    ensure_work(s, std::max(w, fid_work_doubles(s->n) + 5));
+    double *outd = s->d_work + zsum_work_doubles(s->n);
+    timed(s->stream, P_ZSUM, (double)s->bytes, [&] { launch_zsum(s->buf, s->dt, s->n, s->d_work, outd, s->stream); });
+    res.resize(s->n + 1);
+    hipchk(hipMemcpyAsync(res.data(), outd, (s->n + 1) * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+           "hipMemcpyAsync");
+    hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+}
+
+qs_status qs_expect_z(qs_state *s, double *out)
+{
+    return guard([&] {
+        need(s != nullptr && out != nullptr, "NULL argument");
+        std::vector<double> r;
+        zsum(s, r);
+        for (int q = 0; q < s->n; ++q)
+            out[q] = r[0] - 2.0 * r[1 + s->sigma[q]];
+    });
+}
+
+qs_status qs_norm(qs_state *s, double *out)
+{
+    return guard([&] {
+        need(s != nullptr && out != nullptr, "NULL argument");
+        std::vector<double> r;
+        zsum(s, r);
+        *out = r[0];
+    });
+}
+
+qs_status qs_fidelity(qs_state *a, qs_state *b, double *loss, double *max_abs_diff)
+{
+    return guard([&] {
+        need(a != nullptr && b != nullptr, "NULL state");
+        need(a->n == b->n, "states differ in qubit count");
+        const int n = a->n;
+        std::vector<int> inv_a(n), map_b(n);
+        for (int q = 0; q < n; ++q)
+            inv_a[a->sigma[q]] = q;
+        for (int p = 0; p < n; ++p)
+            map_b[p] = b->sigma[inv_a[p]];
+        // b's pending work must finish before a's stream reads it
+        hipchk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        ensure_work(a, std::max(fid_work_doubles(n) + 5, zsum_work_doubles(n) + (size_t)n + 1));
+        double *outd = a->d_work + fid_work_doubles(n);
+        timed(a->stream, P_FID, (double)(a->bytes + b->bytes),
+              [&] { launch_fidelity(a->buf, a->dt, b->buf, b->dt, n, map_b, a->d_work, outd, a->stream); });
+        double r[5];
+        hipchk(hipMemcpyAsync(r, outd, sizeof r, hipMemcpyDeviceToHost, a->stream), "hipMemcpyAsync");
+        hipchk(hipStreamSynchronize(a->stream), "hipStreamSynchronize");
+        const double ov = r[0] * r[0] + r[1] * r[1];
+        if (loss)
+            *loss = 1.0 - ov / (r[2] * r[3]);
+        if (max_abs_diff)
+            *max_abs_diff = r[4];
+    });
+}
+
+qs_status qs_profile_enable(int on)
+{
+    return guard([&] {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_on = on != 0;
+    });
+}
+
+qs_status qs_profile_read(qs_profile_entry *out, int cap, int *n_out)
+{
+    return guard([&] {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        int64_t cnt[P_NCLASS] = {};
+        double ms[P_NCLASS] = {}, by[P_NCLASS] = {};
+        for (const ProfRec &r : g_recs) {
+            hipchk(hipEventSynchronize(r.b), "hipEventSynchronize");
+            float t = 0;
+            hipchk(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+            cnt[r.cls] += 1;
+            ms[r.cls] += t;
+            by[r.cls] += r.bytes;
+            g_pool.push_back(r.a);
+            g_pool.push_back(r.b);
+        }
+        g_recs.clear();
+        int w = 0;
+        for (int c = 0; c < P_NCLASS; ++c) {
+            if (cnt[c] == 0)
+                continue;
+            if (out && w < cap) {
+                std::memset(&out[w], 0, sizeof out[w]);
+                std::strncpy(out[w].name, PROF_NAMES[c], sizeof out[w].name - 1);
+                out[w].launches = cnt[c];
+                out[w].total_ms = ms[c];
+                out[w].bytes = by[c];
+            }
+            ++w;
+        }
+        if (n_out)
+            *n_out = w;
+    });
+}
+
+}  // extern "C"

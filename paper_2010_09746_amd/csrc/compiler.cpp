@@ -1,0 +1,663 @@
+// Circuit compiler: dependency DAG with exact commutation, the
+// permutation-inserting pass (paper, Section 3, Algorithm 1) and the lowering
+// of its output to device launches (fused tile passes, data movement, plain
+// gates).
+//
+// Reading of the pass (the paper leaves these points open):
+//  * qubit q is local iff sigma(q) < m; a gate is local iff every qubit it acts
+//    on non-diagonally is local (a control or CZ is diagonal), so a CNOT with a
+//    global control and local target is local (Sections 2 and 4, Appendix C);
+//  * DAG edges join every pair of gates that share a qubit and do not commute
+//    exactly: gates commute when, on each shared qubit, both act diagonally or
+//    both act as a matrix in span{I, X}, or when they are identical (Section 3);
+//  * a candidate exchange (l, g) swaps the positions of qubits l and g; its
+//    score is the number of remaining gates that become schedulable (local,
+//    with every predecessor scheduled or itself counted);
+//  * candidates run over l, then g, in ascending qubit index; the first strict
+//    maximum wins; the fallback gate is the lowest-index ready gate.
+//
+// Only exchanges whose incoming qubit g is the non-diagonal target of a gate
+// that is ready under the current placement (or becomes ready through gates
+// already counted) can raise the score, so only those g are scored.  Other
+// exchanges cannot beat the running maximum, and the chosen exchange is the
+// one a full scan of all m(n-m) candidates picks.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <functional>
+#include <queue>
+
+#include "internal.h"
+
+namespace qsim {
+
+int matrix_action(const double *u)
+{
+    if (u[2] == 0 && u[3] == 0 && u[4] == 0 && u[5] == 0)
+        return ACT_Z;
+    if (u[0] == u[6] && u[1] == u[7] && u[2] == u[4] && u[3] == u[5])
+        return ACT_X;
+    return ACT_G;
+}
+
+GateInfo analyse(const qs_gate &g)
+{
+    GateInfo gi{};
+    gi.kind = g.kind;
+    gi.q0 = g.q0;
+    gi.q1 = g.q1;
+    gi.u = g.u;
+    switch (g.kind) {
+    case QS_GATE_U:
+        gi.nq = 1;
+        gi.act0 = matrix_action(g.u);
+        gi.act1 = ACT_NONE;
+        gi.target = gi.act0 == ACT_Z ? -1 : g.q0;
+        break;
+    case QS_GATE_CX:
+        gi.nq = 2;
+        gi.act0 = ACT_Z;
+        gi.act1 = ACT_X;
+        gi.target = g.q1;
+        break;
+    case QS_GATE_CZ:
+        gi.nq = 2;
+        gi.act0 = gi.act1 = ACT_Z;
+        gi.target = -1;
+        break;
+    case QS_GATE_CU:
+        gi.nq = 2;
+        gi.act0 = ACT_Z;
+        gi.act1 = matrix_action(g.u);
+        gi.target = gi.act1 == ACT_Z ? -1 : g.q1;
+        break;
+    default:
+        fail(QS_ERR_ARG, "unknown gate kind " + std::to_string(g.kind));
+    }
+    return gi;
+}
+
+static int act_on(const GateInfo &gi, int q)
+{
+    if (q == gi.q0)
+        return gi.act0;
+    if (gi.nq == 2 && q == gi.q1)
+        return gi.act1;
+    return ACT_NONE;
+}
+
+bool gates_commute(const qs_gate &a, const GateInfo &ia, const qs_gate &b, const GateInfo &ib)
+{
+    if (a.kind == b.kind && a.q0 == b.q0 && a.q1 == b.q1 && std::memcmp(a.u, b.u, sizeof a.u) == 0)
+        return true;
+    const int qa[2] = {ia.q0, ia.q1};
+    for (int k = 0; k < ia.nq; ++k) {
+        int tb = act_on(ib, qa[k]);
+        if (tb == ACT_NONE)
+            continue;
+        int ta = k == 0 ? ia.act0 : ia.act1;
+        if (!(ta == tb && (ta == ACT_Z || ta == ACT_X)))
+            return false;
+    }
+    return true;
+}
+
+namespace {
+
+struct Dag {
+    std::vector<std::vector<int>> pred, succ;
+};
+
+Dag build_dag(const qs_gate *g, const std::vector<GateInfo> &gi, int n)
+{
+    const int ng = (int)gi.size();
+    Dag d;
+    d.pred.resize(ng);
+    d.succ.resize(ng);
+    std::vector<std::vector<int>> uses(n);
+    std::vector<int> seen(ng, -1);
+    for (int v = 0; v < ng; ++v) {
+        const int qs[2] = {gi[v].q0, gi[v].q1};
+        for (int k = 0; k < gi[v].nq; ++k) {
+            for (int h : uses[qs[k]]) {
+                if (seen[h] == v)
+                    continue;
+                seen[h] = v;
+                if (!gates_commute(g[h], gi[h], g[v], gi[v]))
+                    d.pred[v].push_back(h);
+            }
+        }
+        std::sort(d.pred[v].begin(), d.pred[v].end());
+        for (int h : d.pred[v])
+            d.succ[h].push_back(v);
+        for (int k = 0; k < gi[v].nq; ++k)
+            uses[qs[k]].push_back(v);
+    }
+    return d;
+}
+
+inline bool is_local(const GateInfo &gi, const int *sigma, int m)
+{
+    return gi.target < 0 || sigma[gi.target] < m;
+}
+
+using MinHeap = std::priority_queue<int, std::vector<int>, std::greater<int>>;
+
+class PassState {
+public:
+    PassState(const std::vector<GateInfo> &gi, const Dag &d, int n, int m)
+        : gi_(gi), d_(d), n_(n), m_(m), npend_(gi.size()), tmp_(gi.size(), -1), done_(gi.size(), 0)
+    {
+        for (size_t v = 0; v < gi.size(); ++v) {
+            npend_[v] = (int)d.pred[v].size();
+            if (npend_[v] == 0)
+                frontier_.push_back((int)v);
+        }
+        remaining_ = (int64_t)gi.size();
+    }
+
+    int64_t remaining() const { return remaining_; }
+
+    // Schedule every local gate whose predecessors are scheduled, in program
+    // order (one sweep in index order reaches the fixed point).
+    void sweep(const int *sigma, std::vector<int> &emitted)
+    {
+        MinHeap h(std::greater<int>(), frontier_);
+        std::vector<int> blocked;
+        while (!h.empty()) {
+            int v = h.top();
+            h.pop();
+            if (is_local(gi_[v], sigma, m_)) {
+                emitted.push_back(v);
+                mark_done(v, &h);
+            } else {
+                blocked.push_back(v);
+            }
+        }
+        frontier_.swap(blocked);
+    }
+
+    // Number of not-scheduled gates that become schedulable under sigma;
+    // optionally collects the non-diagonal targets (qubits) of gates that are
+    // reached (all predecessors done or counted) but are not local.
+    int64_t closure(const int *sigma, std::vector<char> *reach_targets)
+    {
+        MinHeap h(std::greater<int>(), frontier_);
+        touched_.clear();
+        int64_t cnt = 0;
+        while (!h.empty()) {
+            int v = h.top();
+            h.pop();
+            if (!is_local(gi_[v], sigma, m_)) {
+                if (reach_targets)
+                    (*reach_targets)[gi_[v].target] = 1;
+                continue;
+            }
+            ++cnt;
+            for (int s : d_.succ[v]) {
+                if (tmp_[s] < 0) {
+                    tmp_[s] = npend_[s];
+                    touched_.push_back(s);
+                }
+                if (--tmp_[s] == 0)
+                    h.push(s);
+            }
+        }
+        for (int s : touched_)
+            tmp_[s] = -1;
+        return cnt;
+    }
+
+    // lowest-index ready gate (Algorithm 1 fallback); schedules it
+    int take_first_ready()
+    {
+        auto it = std::min_element(frontier_.begin(), frontier_.end());
+        int v = *it;
+        frontier_.erase(it);
+        std::vector<int> newly;
+        mark_done(v, nullptr, &newly);
+        frontier_.insert(frontier_.end(), newly.begin(), newly.end());
+        return v;
+    }
+
+private:
+    void mark_done(int v, MinHeap *h, std::vector<int> *newly = nullptr)
+    {
+        done_[v] = 1;
+        --remaining_;
+        for (int s : d_.succ[v])
+            if (--npend_[s] == 0) {
+                if (h)
+                    h->push(s);
+                if (newly)
+                    newly->push_back(s);
+            }
+    }
+
+    const std::vector<GateInfo> &gi_;
+    const Dag &d_;
+    int n_, m_;
+    std::vector<int> npend_, tmp_, touched_;
+    std::vector<char> done_;
+    std::vector<int> frontier_;
+    int64_t remaining_;
+};
+
+}  // namespace
+
+std::vector<Instr> run_pass(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned,
+                            const std::vector<int> &sigma0, PassStats *st)
+{
+    std::vector<GateInfo> gi(ng);
+    for (int64_t v = 0; v < ng; ++v)
+        gi[v] = analyse(g[v]);
+    Dag d = build_dag(g, gi, n);
+    PassState ps(gi, d, n, m);
+    std::vector<int> sigma = sigma0, cur(n), cand(n), best(n);
+    std::vector<Instr> out;
+    std::vector<int> emitted;
+    std::vector<char> targets(n);
+    PassStats s{};
+    while (ps.remaining() > 0) {
+        emitted.clear();
+        ps.sweep(sigma.data(), emitted);
+        for (int v : emitted)
+            out.push_back(Instr{0, v, {}});
+        s.n_apply += (int64_t)emitted.size();
+        if (ps.remaining() == 0)
+            break;
+
+        cur = sigma;
+        int64_t base = 0;
+        int swaps = 0;
+        for (int step = 0; step < r; ++step) {
+            std::fill(targets.begin(), targets.end(), 0);
+            ps.closure(cur.data(), &targets);
+            int64_t best_a = base;
+            bool found = false;
+            for (int l = 0; l < n; ++l) {
+                if (!(cur[l] < m && cur[l] >= pinned))
+                    continue;
+                for (int gq = 0; gq < n; ++gq) {
+                    if (cur[gq] < m || !targets[gq])
+                        continue;
+                    cand = cur;
+                    cand[l] = cur[gq];
+                    cand[gq] = cur[l];
+                    int64_t a = ps.closure(cand.data(), nullptr);
+                    if (a > best_a) {
+                        best_a = a;
+                        best = cand;
+                        found = true;
+                    }
+                }
+            }
+            if (!found)
+                break;
+            cur = best;
+            base = best_a;
+            ++swaps;
+        }
+        if (swaps > 0) {
+            sigma = cur;
+            out.push_back(Instr{1, -1, sigma});
+            ++s.n_perm;
+            s.n_swaps += swaps;
+        } else {
+            int v = ps.take_first_ready();
+            out.push_back(Instr{2, v, {}});
+            ++s.n_global;
+        }
+    }
+    if (st)
+        *st = s;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// lowering
+
+void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt)
+{
+    int lr = reg_bits_opt > 0 ? reg_bits_opt : (dt == QS_C128 ? 4 : 4);
+    lr = std::min(lr, 5);
+    lr = std::max(lr, k - 10);   // at most 1024 threads
+    lr = std::min(lr, k - 6);    // at least one wavefront
+    lr = std::max(lr, 1);
+    *log_r = lr;
+    *log_nt = k - lr;
+}
+
+namespace {
+
+// A gate lowered to tile-local form, before register slots are assigned.
+struct LGate {
+    int kind;        // OP_U / OP_X / OP_DIAG / OP_NEG
+    int tb;          // tile bit of the non-diagonal target (OP_U/OP_X), DIAG target tile bit or -1
+    uint32_t cmask;
+    uint64_t hmask, hbit;
+    double m[8];
+    int q[2], nq;    // logical qubits (for in-segment dependencies)
+    int src;         // index into the source gate array
+};
+
+LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &sigma_phys,
+                 const std::vector<int> &tile_bit_of_pos)
+{
+    LGate L{};
+    L.src = -1;
+    L.nq = gi.nq;
+    L.q[0] = gi.q0;
+    L.q[1] = gi.q1;
+    std::memcpy(L.m, g.u, sizeof L.m);
+    auto add_ctrl = [&](int q) {
+        int p = sigma_phys[q];
+        int tb = tile_bit_of_pos[p];
+        if (tb >= 0)
+            L.cmask |= 1u << tb;
+        else
+            L.hmask |= 1ull << p;
+    };
+    auto set_diag_target = [&](int q, const double *d0, const double *d1) {
+        int p = sigma_phys[q];
+        int tb = tile_bit_of_pos[p];
+        L.kind = OP_DIAG;
+        L.tb = tb;
+        L.hbit = tb >= 0 ? 0 : (1ull << p);
+        L.m[0] = d0[0];
+        L.m[1] = d0[1];
+        L.m[2] = d1[0];
+        L.m[3] = d1[1];
+    };
+    auto need_tile = [&](int q) {
+        int tb = tile_bit_of_pos[sigma_phys[q]];
+        if (tb < 0)
+            fail(QS_ERR_STATE, "internal: non-local target in tile segment");
+        return tb;
+    };
+    switch (g.kind) {
+    case QS_GATE_U:
+        if (gi.act0 == ACT_Z) {
+            set_diag_target(g.q0, &g.u[0], &g.u[6]);
+        } else {
+            L.kind = OP_U;
+            L.tb = need_tile(g.q0);
+        }
+        break;
+    case QS_GATE_CX:
+        L.kind = OP_X;
+        L.tb = need_tile(g.q1);
+        add_ctrl(g.q0);
+        break;
+    case QS_GATE_CZ:
+        L.kind = OP_NEG;
+        L.tb = -1;
+        add_ctrl(g.q0);
+        add_ctrl(g.q1);
+        break;
+    case QS_GATE_CU:
+        if (gi.act1 == ACT_Z) {
+            set_diag_target(g.q1, &g.u[0], &g.u[6]);
+        } else {
+            L.kind = OP_U;
+            L.tb = need_tile(g.q1);
+        }
+        add_ctrl(g.q0);
+        break;
+    }
+    return L;
+}
+
+// Order the gates of one tile pass and insert register re-layouts.  The gates
+// may be reordered only along the commutation DAG restricted to the segment.
+int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::vector<GateInfo> &gi,
+                     int k, int log_r, std::vector<TileOp> &ops)
+{
+    const int cnt = (int)lg.size();
+    // in-segment predecessors
+    std::vector<std::vector<int>> pred(cnt);
+    for (int v = 0; v < cnt; ++v)
+        for (int h = 0; h < v; ++h) {
+            bool share = false;
+            for (int a = 0; a < lg[h].nq; ++a)
+                for (int b = 0; b < lg[v].nq; ++b)
+                    share |= lg[h].q[a] == lg[v].q[b];
+            if (share && !gates_commute(g[lg[h].src], gi[lg[h].src], g[lg[v].src], gi[lg[v].src]))
+                pred[v].push_back(h);
+        }
+    std::vector<char> emitted(cnt, 0);
+    int left = cnt, remaps = 0;
+    const int R = log_r;
+    int regs[8];
+    bool have = false;
+    auto in_regs = [&](int tb) {
+        if (!have)
+            return -1;
+        for (int s = 0; s < R; ++s)
+            if (regs[s] == tb)
+                return s;
+        return -1;
+    };
+    auto ready = [&](int v) {
+        for (int h : pred[v])
+            if (!emitted[h])
+                return false;
+        return true;
+    };
+    auto needs_reg = [&](int v) { return lg[v].kind == OP_U || lg[v].kind == OP_X; };
+    while (left > 0) {
+        bool progress = true;
+        while (progress) {
+            progress = false;
+            for (int v = 0; v < cnt; ++v) {
+                if (emitted[v] || !ready(v))
+                    continue;
+                int slot = -1;
+                if (!have)
+                    continue;   // ops act on register data: a layout must exist
+                if (needs_reg(v)) {
+                    slot = in_regs(lg[v].tb);
+                    if (slot < 0)
+                        continue;
+                }
+                TileOp op{};
+                op.kind = lg[v].kind;
+                op.slot = needs_reg(v) ? slot : lg[v].tb;
+                op.cmask = lg[v].cmask;
+                op.hmask = lg[v].hmask;
+                op.hbit = lg[v].hbit;
+                std::memcpy(op.m, lg[v].m, sizeof op.m);
+                ops.push_back(op);
+                emitted[v] = 1;
+                --left;
+                progress = true;
+            }
+        }
+        if (left == 0)
+            break;
+        // re-layout: targets of ready gates first, then of later gates
+        std::vector<int> want;
+        auto add = [&](int tb) {
+            if (tb >= 0 && std::find(want.begin(), want.end(), tb) == want.end())
+                want.push_back(tb);
+        };
+        for (int v = 0; v < cnt; ++v)
+            if (!emitted[v] && ready(v) && needs_reg(v))
+                add(lg[v].tb);
+        for (int v = 0; v < cnt && (int)want.size() < R; ++v)
+            if (!emitted[v] && needs_reg(v))
+                add(lg[v].tb);
+        if (have)
+            for (int s = 0; s < R; ++s)
+                add(regs[s]);
+        for (int b = k - 1; b >= 0 && (int)want.size() < R; --b)
+            add(b);
+        TileOp op{};
+        op.kind = OP_REMAP;
+        uint32_t packed = 0;
+        for (int s = 0; s < R; ++s) {
+            regs[s] = want[s];
+            packed |= (uint32_t)want[s] << (4 * s);
+        }
+        op.regs = packed;
+        ops.push_back(op);
+        have = true;
+        ++remaps;
+    }
+    return remaps;
+}
+
+}  // namespace
+
+void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0_in,
+                     const qs_run_opts &o, Program &p)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (n < 1 || n > MAX_COMPILE_QUBITS)
+        fail(QS_ERR_ARG, "n out of range");
+    p.n = n;
+    p.dt = dt;
+    p.opts = o;
+    p.sigma0.resize(n);
+    for (int q = 0; q < n; ++q)
+        p.sigma0[q] = sigma0_in ? sigma0_in[q] : q;
+    {
+        std::vector<char> seen(n, 0);
+        for (int q = 0; q < n; ++q) {
+            if (p.sigma0[q] < 0 || p.sigma0[q] >= n || seen[p.sigma0[q]])
+                fail(QS_ERR_ARG, "sigma0 is not a permutation");
+            seen[p.sigma0[q]] = 1;
+        }
+    }
+    std::vector<GateInfo> gi(ng);
+    for (int64_t v = 0; v < ng; ++v) {
+        const qs_gate &x = g[v];
+        if (x.q0 < 0 || x.q0 >= n)
+            fail(QS_ERR_ARG, "gate " + std::to_string(v) + ": qubit out of range");
+        if (x.kind != QS_GATE_U && (x.q1 < 0 || x.q1 >= n || x.q1 == x.q0))
+            fail(QS_ERR_ARG, "gate " + std::to_string(v) + ": bad second qubit");
+        gi[v] = analyse(x);
+    }
+    p.stats = qs_program_stats{};
+    p.stats.n_gates = ng;
+    p.launches.clear();
+    p.ops.clear();
+    std::vector<int> sphys = p.sigma0;
+
+    auto plain = [&](int64_t v) {
+        Launch L;
+        L.type = L_PLAIN;
+        L.gate = g[v];
+        L.gate.q0 = sphys[g[v].q0];
+        L.gate.q1 = g[v].kind == QS_GATE_U ? -1 : sphys[g[v].q1];
+        p.launches.push_back(L);
+        ++p.stats.n_plain;
+    };
+
+    if (o.form == QS_FORM_PLAIN) {
+        for (int64_t v = 0; v < ng; ++v) {
+            p.instrs.push_back(Instr{0, (int)v, {}});
+            plain(v);
+        }
+        p.sigma_final = sphys;
+        p.stats.n_apply = ng;
+    } else if (o.form == QS_FORM_PASS) {
+        const int k = std::min(o.k_tile, n);
+        if (k < 1)
+            fail(QS_ERR_ARG, "k_tile must be >= 1");
+        if (o.max_swaps < 1)
+            fail(QS_ERR_ARG, "max_swaps must be >= 1");
+        if (o.pinned < 0 || o.pinned > k)
+            fail(QS_ERR_ARG, "pinned must be in [0, k_tile]");
+        if (o.perm_exec != QS_PERM_MOVE && o.perm_exec != QS_PERM_RELABEL)
+            fail(QS_ERR_ARG, "unknown perm_exec");
+        PassStats ps;
+        p.instrs = run_pass(g, ng, n, k, o.max_swaps, o.pinned, p.sigma0, &ps);
+        p.stats.n_apply = ps.n_apply;
+        p.stats.n_perm = ps.n_perm;
+        p.stats.n_global = ps.n_global;
+        p.stats.n_swaps = ps.n_swaps;
+
+        // tile passes need 7 <= k and a tile that fits in one CU's LDS; a larger
+        // local set (e.g. a pass planned for several devices) runs its
+        // segments gate by gate
+        const bool tiled = k >= MIN_TILE_BITS && (size_t(dt == QS_C64 ? 8 : 16) << k) <= MAX_TILE_BYTES;
+        int log_r = 0, log_nt = 0;
+        if (tiled)
+            tile_shape(k, dt, o.reg_bits, &log_r, &log_nt);
+        std::vector<int> spass = p.sigma0;
+        size_t i = 0;
+        while (i < p.instrs.size()) {
+            const Instr &I = p.instrs[i];
+            if (I.type == 1) {
+                spass = I.sigma;
+                if (o.perm_exec == QS_PERM_MOVE) {
+                    Launch L;
+                    L.type = L_MOVE;
+                    L.pi.resize(n);
+                    for (int q = 0; q < n; ++q)
+                        L.pi[sphys[q]] = spass[q];
+                    p.launches.push_back(L);
+                    ++p.stats.n_move_passes;
+                    sphys = spass;
+                }
+                ++i;
+                continue;
+            }
+            if (I.type == 2) {
+                plain(I.gate);
+                ++i;
+                continue;
+            }
+            // a run of local ApplyGate instructions = one segment
+            size_t j = i;
+            while (j < p.instrs.size() && p.instrs[j].type == 0)
+                ++j;
+            if (!tiled) {
+                for (size_t t = i; t < j; ++t)
+                    plain(p.instrs[t].gate);
+                i = j;
+                continue;
+            }
+            // tile positions: physical positions of the k local qubits
+            std::vector<int> pos;
+            for (int q = 0; q < n; ++q)
+                if (spass[q] < k)
+                    pos.push_back(sphys[q]);
+            std::sort(pos.begin(), pos.end());
+            std::vector<int> tbit(n, -1);
+            for (int b = 0; b < k; ++b)
+                tbit[pos[b]] = b;
+            const size_t chunk = o.max_fuse > 0 ? (size_t)o.max_fuse : (j - i);
+            for (size_t c0 = i; c0 < j; c0 += chunk) {
+                size_t c1 = std::min(j, c0 + chunk);
+                std::vector<LGate> lg;
+                for (size_t t = c0; t < c1; ++t) {
+                    int v = p.instrs[t].gate;
+                    LGate L = lower_gate(g[v], gi[v], sphys, tbit);
+                    L.src = v;
+                    lg.push_back(L);
+                }
+                Launch L;
+                L.type = L_TILE;
+                L.k = k;
+                L.log_r = log_r;
+                L.log_nt = log_nt;
+                L.pos = pos;
+                L.op_begin = (int)p.ops.size();
+                p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops);
+                L.op_count = (int)p.ops.size() - L.op_begin;
+                p.launches.push_back(L);
+                ++p.stats.n_tile_passes;
+            }
+            i = j;
+        }
+        p.sigma_final = sphys;
+    } else {
+        fail(QS_ERR_ARG, "unknown form");
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    p.stats.compile_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+}  // namespace qsim

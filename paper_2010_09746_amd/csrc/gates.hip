@@ -1,0 +1,263 @@
+// Plain-form kernels: one launch per gate (paper, Section 2: gates update
+// amplitudes in pairs), the in-place data movement of PermuteQubits and state
+// preparation.
+//
+// Every kernel is bound by HBM traffic.  Threads take consecutive pair indices,
+// so for a target position t >= log2(64) a wavefront reads two contiguous
+// 64-amplitude runs; for lower t the pairs interleave inside the same cache
+// lines and both halves of each line are consumed by the same wavefront.
+#include <hip/hip_runtime.h>
+
+#include "common.cuh"
+#include "kernels.h"
+
+namespace qsim {
+
+namespace {
+
+constexpr int NT = 256;   // threads per block
+constexpr int UNR = 4;    // pairs per thread, loads issued before use
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t x, int b)
+{
+    const uint64_t lo = x & ((1ull << b) - 1);
+    return ((x >> b) << (b + 1)) | lo;
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_set_basis(typename Cx<R>::T *s, uint64_t N, uint64_t x)
+{
+    using C = typename Cx<R>::T;
+    const uint64_t i0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t i = i0 + (uint64_t)u * NT;
+        if (i < N) {
+            C v;
+            v.x = i == x ? R(1) : R(0);
+            v.y = R(0);
+            s[i] = v;
+        }
+    }
+}
+
+// (a_i, a_j) <- U (a_i, a_j) for j = i | 2^t, optionally only where bit c = 1.
+template <typename R, bool CTRL>
+__global__ __launch_bounds__(NT) void k_pair_u(typename Cx<R>::T *__restrict__ s, uint64_t npairs,
+                                               int t, int c_lo, int c_hi, uint64_t cbit, Mat<R> m)
+{
+    using C = typename Cx<R>::T;
+    const uint64_t p0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
+    C a[UNR], b[UNR];
+    uint64_t ii[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t p = p0 + (uint64_t)u * NT;
+        uint64_t i;
+        if (CTRL)
+            i = insert_zero(insert_zero(p, c_lo), c_hi) | cbit;
+        else
+            i = insert_zero(p, t);
+        ii[u] = i;
+        if (p < npairs) {
+            a[u] = s[i];
+            b[u] = s[i | (1ull << t)];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t p = p0 + (uint64_t)u * NT;
+        if (p < npairs) {
+            C x = a[u], y = b[u];
+            s[ii[u]] = m.row0(x, y);
+            s[ii[u] | (1ull << t)] = m.row1(x, y);
+        }
+    }
+}
+
+// controlled X: exchange a_i and a_j where bit c = 1
+template <typename R>
+__global__ __launch_bounds__(NT) void k_cx(typename Cx<R>::T *__restrict__ s, uint64_t nquads, int t,
+                                           int lo, int hi, uint64_t cbit)
+{
+    using C = typename Cx<R>::T;
+    const uint64_t p0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
+    C a[UNR], b[UNR];
+    uint64_t ii[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t p = p0 + (uint64_t)u * NT;
+        ii[u] = insert_zero(insert_zero(p, lo), hi) | cbit;
+        if (p < nquads) {
+            a[u] = s[ii[u]];
+            b[u] = s[ii[u] | (1ull << t)];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t p = p0 + (uint64_t)u * NT;
+        if (p < nquads) {
+            s[ii[u]] = b[u];
+            s[ii[u] | (1ull << t)] = a[u];
+        }
+    }
+}
+
+// controlled Z: negate a_i where both bits are 1
+template <typename R>
+__global__ __launch_bounds__(NT) void k_cz(typename Cx<R>::T *__restrict__ s, uint64_t nquads, int lo,
+                                           int hi, uint64_t both)
+{
+    using C = typename Cx<R>::T;
+    const uint64_t p0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
+    C a[UNR];
+    uint64_t ii[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t p = p0 + (uint64_t)u * NT;
+        ii[u] = insert_zero(insert_zero(p, lo), hi) | both;
+        if (p < nquads)
+            a[u] = s[ii[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t p = p0 + (uint64_t)u * NT;
+        if (p < nquads) {
+            C v = a[u];
+            v.x = -v.x;
+            v.y = -v.y;
+            s[ii[u]] = v;
+        }
+    }
+}
+
+// In-place exchange of chunks of 2^c0 amplitudes: chunk x0 and chunk J(x0),
+// where J moves bit p of the index to bit pi[p] (an involution, identity on
+// positions below c0).  The pair is exchanged by the chunk with x0 < J(x0).
+struct Involution {
+    int n_moved;
+    uint8_t from[48], to[48];
+    uint64_t moved_mask;
+};
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_involution(typename Cx<R>::T *__restrict__ s, uint64_t N, int c0,
+                                                   Involution J)
+{
+    using C = typename Cx<R>::T;
+    const uint64_t i0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        uint64_t x = i0 + (uint64_t)u * NT;
+        if (x >= N)
+            continue;
+        uint64_t y = x & ~J.moved_mask;
+#pragma unroll
+        for (int k = 0; k < MAX_QUBITS; ++k)
+            if (k < J.n_moved)
+                y |= ((x >> J.from[k]) & 1ull) << J.to[k];
+        if (x < y) {
+            C a = s[x], b = s[y];
+            s[x] = b;
+            s[y] = a;
+        }
+    }
+    (void)c0;
+}
+
+inline unsigned blocks_for(uint64_t items)
+{
+    uint64_t b = (items + (uint64_t)NT * UNR - 1) / ((uint64_t)NT * UNR);
+    return (unsigned)(b ? b : 1);
+}
+
+template <typename R>
+void plain_gate_t(void *state, int n, const qs_gate &g, hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    C *s = reinterpret_cast<C *>(state);
+    switch (g.kind) {
+    case QS_GATE_U: {
+        uint64_t np = 1ull << (n - 1);
+        hipLaunchKernelGGL((k_pair_u<R, false>), dim3(blocks_for(np)), dim3(NT), 0, st, s, np, g.q0, 0, 0,
+                           0ull, Mat<R>(g.u));
+        break;
+    }
+    case QS_GATE_CU: {
+        uint64_t nq = 1ull << (n - 2);
+        int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
+        hipLaunchKernelGGL((k_pair_u<R, true>), dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, g.q1, lo, hi,
+                           1ull << g.q0, Mat<R>(g.u));
+        break;
+    }
+    case QS_GATE_CX: {
+        uint64_t nq = 1ull << (n - 2);
+        int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
+        hipLaunchKernelGGL(k_cx<R>, dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, g.q1, lo, hi, 1ull << g.q0);
+        break;
+    }
+    case QS_GATE_CZ: {
+        uint64_t nq = 1ull << (n - 2);
+        int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
+        hipLaunchKernelGGL(k_cz<R>, dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, lo, hi,
+                           (1ull << g.q0) | (1ull << g.q1));
+        break;
+    }
+    default:
+        fail(QS_ERR_ARG, "unknown gate kind");
+    }
+    check_launch("plain gate");
+}
+
+}  // namespace
+
+void launch_set_basis(void *state, qs_dtype dt, int n, uint64_t x, hipStream_t st)
+{
+    uint64_t N = 1ull << n;
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_set_basis<float>, dim3(blocks_for(N)), dim3(NT), 0, st,
+                           reinterpret_cast<Cplx<float> *>(state), N, x);
+    else
+        hipLaunchKernelGGL(k_set_basis<double>, dim3(blocks_for(N)), dim3(NT), 0, st,
+                           reinterpret_cast<Cplx<double> *>(state), N, x);
+    check_launch("set_basis");
+}
+
+void launch_plain_gate(void *state, qs_dtype dt, int n, const qs_gate &g, hipStream_t st)
+{
+    if (g.kind != QS_GATE_U && n < 2)
+        fail(QS_ERR_ARG, "two-qubit gate on a one-qubit state");
+    if (dt == QS_C64)
+        plain_gate_t<float>(state, n, g, st);
+    else
+        plain_gate_t<double>(state, n, g, st);
+}
+
+void launch_involution(void *state, qs_dtype dt, int n, const std::vector<int> &pi, hipStream_t st)
+{
+    Involution J{};
+    int c0 = n;
+    for (int p = 0; p < n; ++p) {
+        if (pi[p] != p) {
+            if (pi[pi[p]] != p)
+                fail(QS_ERR_ARG, "internal: position map is not an involution");
+            J.from[J.n_moved] = (uint8_t)p;
+            J.to[J.n_moved] = (uint8_t)pi[p];
+            J.moved_mask |= 1ull << p;
+            ++J.n_moved;
+            c0 = p < c0 ? p : c0;
+        }
+    }
+    if (J.n_moved == 0)
+        return;
+    uint64_t N = 1ull << n;
+    if (dt == QS_C64)
+        hipLaunchKernelGGL(k_involution<float>, dim3(blocks_for(N)), dim3(NT), 0, st,
+                           reinterpret_cast<Cplx<float> *>(state), N, c0, J);
+    else
+        hipLaunchKernelGGL(k_involution<double>, dim3(blocks_for(N)), dim3(NT), 0, st,
+                           reinterpret_cast<Cplx<double> *>(state), N, c0, J);
+    check_launch("involution");
+}
+
+}  // namespace qsim

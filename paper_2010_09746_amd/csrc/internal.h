@@ -1,0 +1,137 @@
+// Internal declarations shared by the host runtime, the compiler and the HIP
+// kernels of the simulator library.  Not part of the public boundary
+// (include/qsim.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qsim.h"
+
+namespace qsim {
+
+// ---------------------------------------------------------------------------
+// gate analysis
+
+// How a gate acts on one of its qubits.
+enum Act : int { ACT_NONE = 0, ACT_Z = 1, ACT_X = 2, ACT_G = 3 };
+
+struct GateInfo {
+    int kind, q0, q1;
+    int act0, act1;   // action on q0 / q1
+    int nq;           // 1 or 2
+    int target;       // qubit acted on non-diagonally, -1 if the gate is diagonal
+    const double *u;  // matrix of the source record
+};
+
+int matrix_action(const double *u);
+GateInfo analyse(const qs_gate &g);
+bool gates_commute(const qs_gate &a, const GateInfo &ia, const qs_gate &b, const GateInfo &ib);
+
+// ---------------------------------------------------------------------------
+// tile kernel operations
+
+enum TileOpKind : int32_t {
+    OP_U = 0,      // dense 2x2 on register slot `slot`
+    OP_X = 1,      // exchange the pair on register slot `slot`
+    OP_DIAG = 2,   // multiply by d0 (m[0..1]) / d1 (m[2..3]) selected by a target bit
+    OP_NEG = 3,    // negate where all bits of cmask (tile) and hmask (outside) are 1
+    OP_REMAP = 4,  // move amplitudes through LDS to a new register layout
+};
+
+// One operation of a fused tile pass (96 bytes).  Control conditions: the
+// tile-local index must have every bit of cmask set and the tile's base
+// position every bit of hmask set.
+struct TileOp {
+    int32_t kind;
+    int32_t slot;      // OP_U/OP_X: register slot; OP_DIAG: tile bit of the target or -1
+    uint32_t cmask;
+    uint32_t regs;     // OP_REMAP: register tile bits, 4 bits each (slot s at bits 4s..4s+3)
+    uint64_t hmask;
+    uint64_t hbit;     // OP_DIAG with out-of-tile target: its position bit
+    double m[8];
+};
+static_assert(sizeof(TileOp) == 96, "TileOp layout");
+
+constexpr int MAX_TILE_BITS = 15;
+constexpr int MIN_TILE_BITS = 7;
+constexpr int MAX_QUBITS = 34;          // states
+constexpr int MAX_COMPILE_QUBITS = 63;  // host-only compilation
+constexpr size_t MAX_TILE_BYTES = 131072;   // LDS of one tile (per workgroup)
+
+// Kernel arguments of one tile pass, passed by value.
+struct TileArgs {
+    void *state;
+    const TileOp *ops;
+    int32_t n_ops;
+    int32_t n_hi;                 // positions outside the tile
+    uint8_t pos[16];              // tile bit b -> physical position (ascending)
+    uint8_t perm[16];             // store: tile bit b moves to tile bit perm[b]
+    uint8_t pinv[16];             // inverse of perm
+    int32_t has_perm;
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// compiled program
+
+enum LaunchType : int { L_TILE = 0, L_PLAIN = 1, L_MOVE = 2 };
+
+struct Launch {
+    int type = L_PLAIN;
+    // L_TILE
+    int k = 0, log_r = 0, log_nt = 0;
+    std::vector<int> pos;         // sorted tile positions
+    int op_begin = 0, op_count = 0;
+    std::vector<int> perm;        // optional tile-bit permutation on store (empty = none)
+    // L_PLAIN
+    qs_gate gate{};               // qubits already mapped to physical positions
+    // L_MOVE
+    std::vector<int> pi;          // physical position p moves to pi[p]
+};
+
+struct Instr {
+    int type;                     // 0 apply, 1 perm, 2 global
+    int gate;
+    std::vector<int> sigma;
+};
+
+struct PassStats {
+    int64_t n_apply = 0, n_perm = 0, n_global = 0, n_swaps = 0;
+};
+
+// Pass of Section 3 (Algorithm 1) with the r / pinned extensions.
+std::vector<Instr> run_pass(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned,
+                            const std::vector<int> &sigma0, PassStats *st);
+
+struct Program {
+    int n = 0;
+    qs_dtype dt = QS_C128;
+    qs_run_opts opts{};
+    std::vector<int> sigma0, sigma_final;
+    std::vector<Instr> instrs;
+    std::vector<Launch> launches;
+    std::vector<TileOp> ops;
+    qs_program_stats stats{};
+    // device copy of ops (per device, uploaded on first run)
+    int dev = -1;
+    TileOp *d_ops = nullptr;
+};
+
+void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0,
+                     const qs_run_opts &o, Program &p);
+
+// choose register bits / threads for a tile of k bits
+void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);
+
+// ---------------------------------------------------------------------------
+// error reporting
+
+struct Error {
+    qs_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(qs_status code, const std::string &msg);
+
+}  // namespace qsim

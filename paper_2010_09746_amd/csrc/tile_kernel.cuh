@@ -1,0 +1,317 @@
+// Fused tile pass: one workgroup loads a tile of 2^K amplitudes, applies a run
+// of gates that act on the tile's qubits, and stores the tile back in place.
+//
+// The tile is the set of amplitudes whose physical index has fixed bits
+// outside K chosen positions pos[0..K) (the local qubits of the permutation
+// pass, paper, Section 3).  With pos = 0..K-1 the tile is a contiguous block;
+// when the pass only relabels qubits the tile gathers strided runs.
+//
+// Data path per tile:
+//   HBM -> LDS        coalesced: tile-local index t = j*NT + tid
+//   LDS -> registers  layout chosen per group of gates (OP_REMAP): the
+//                     register slots of a thread hold the 2^LOG_R amplitudes
+//                     whose tile-local indices differ in the LOG_R "register
+//                     bits"; the remaining bits come from the thread id
+//   gates             one-qubit updates and exchanges on register bits run
+//                     inside a thread; diagonal gates and controls on any bit
+//                     (or on a position outside the tile) are evaluated from
+//                     the tile-local index and the tile's base index
+//   registers -> LDS -> HBM  coalesced store
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.cuh"
+
+namespace qsim {
+
+template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
+    using C = typename Cx<R>::T;
+    static constexpr int NT = 1 << LOG_NT, NR = 1 << LOG_R, K = LOG_NT + LOG_R;
+
+    // register slot pair (j, j | 2^S) for pair index jj
+    template <int S> static constexpr int pair_lo(int jj)
+    {
+        return ((jj >> S) << (S + 1)) | (jj & ((1 << S) - 1));
+    }
+
+    template <int S, bool CTRL>
+    static __device__ __forceinline__ void bfly(C (&v)[NR], const Mat<R> &m, uint32_t cm, uint32_t tbase,
+                                                const uint32_t (&offs)[NR])
+    {
+#pragma unroll
+        for (int jj = 0; jj < NR / 2; ++jj) {
+            const int j = pair_lo<S>(jj), j1 = j | (1 << S);
+            const C x = v[j], y = v[j1];
+            const C nx = m.row0(x, y), ny = m.row1(x, y);
+            if (CTRL) {
+                const bool p = ((tbase | offs[j]) & cm) == cm;
+                v[j].x = p ? nx.x : x.x;
+                v[j].y = p ? nx.y : x.y;
+                v[j1].x = p ? ny.x : y.x;
+                v[j1].y = p ? ny.y : y.y;
+            } else {
+                v[j] = nx;
+                v[j1] = ny;
+            }
+        }
+    }
+
+    template <int S>
+    static __device__ __forceinline__ void xswap(C (&v)[NR], uint32_t cm, uint32_t tbase, const uint32_t (&offs)[NR])
+    {
+#pragma unroll
+        for (int jj = 0; jj < NR / 2; ++jj) {
+            const int j = pair_lo<S>(jj), j1 = j | (1 << S);
+            const C x = v[j], y = v[j1];
+            const bool p = ((tbase | offs[j]) & cm) == cm;
+            v[j].x = p ? y.x : x.x;
+            v[j].y = p ? y.y : x.y;
+            v[j1].x = p ? x.x : y.x;
+            v[j1].y = p ? x.y : y.y;
+        }
+    }
+
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_u(int slot, C (&v)[NR], const Mat<R> &m, uint32_t cm,
+                                                      uint32_t tbase, const uint32_t (&offs)[NR])
+    {
+        if constexpr (S < LOG_R) {
+            if (slot == S) {
+                if (cm == 0)
+                    bfly<S, false>(v, m, cm, tbase, offs);
+                else
+                    bfly<S, true>(v, m, cm, tbase, offs);
+            } else {
+                dispatch_u<S + 1>(slot, v, m, cm, tbase, offs);
+            }
+        }
+    }
+
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_x(int slot, C (&v)[NR], uint32_t cm, uint32_t tbase,
+                                                      const uint32_t (&offs)[NR])
+    {
+        if constexpr (S < LOG_R) {
+            if (slot == S)
+                xswap<S>(v, cm, tbase, offs);
+            else
+                dispatch_x<S + 1>(slot, v, cm, tbase, offs);
+        }
+    }
+
+    static __device__ __forceinline__ uint32_t bitperm(uint32_t x, const uint8_t *perm)
+    {
+        uint32_t y = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            y |= ((x >> b) & 1u) << perm[b];
+        return y;
+    }
+
+    // deposit of the tile's register-slot bits j into the positions pos[LOG_NT..K)
+    static __device__ __forceinline__ uint64_t slot_offset(const TileArgs &a, int j)
+    {
+        uint64_t dj = 0;
+#pragma unroll
+        for (int b = 0; b < LOG_R; ++b)
+            if ((j >> b) & 1)
+                dj |= 1ull << a.pos[LOG_NT + b];
+        return dj;
+    }
+
+    static __device__ __forceinline__ void run(const TileArgs &a, unsigned char *lds_raw)
+    {
+        C *lds = reinterpret_cast<C *>(lds_raw);
+        C *st = reinterpret_cast<C *>(a.state);
+        // operations are read with uniform (scalar) loads
+        const __attribute__((address_space(4))) TileOp *ops =
+            (const __attribute__((address_space(4))) TileOp *)(a.ops);
+        const uint32_t tid = threadIdx.x;
+
+        // base index: the tile number with a zero inserted at every tile position
+        // (positions ascending)
+        uint64_t base = blockIdx.x;
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const int p = a.pos[b];
+            base = ((base >> p) << (p + 1)) | (base & ((1ull << p) - 1));
+        }
+        uint64_t dtid = 0;
+#pragma unroll
+        for (int b = 0; b < LOG_NT; ++b)
+            dtid |= (uint64_t)((tid >> b) & 1u) << a.pos[b];
+
+        C v[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            v[j] = st[base + dtid + slot_offset(a, j)];
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            lds[j * NT + tid] = v[j];
+        __syncthreads();
+
+        uint32_t offs[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            offs[j] = 0;
+        uint32_t tbase = 0;
+        bool have = false;
+
+        for (int oi = 0; oi < a.n_ops; ++oi) {
+            const __attribute__((address_space(4))) TileOp &op = ops[oi];
+            const int kind = op.kind;
+            if (kind == OP_REMAP) {
+                if (have) {
+#pragma unroll
+                    for (int j = 0; j < NR; ++j)
+                        lds[tbase | offs[j]] = v[j];
+                    __syncthreads();
+                }
+                const uint32_t regs = op.regs;
+                uint32_t regmask = 0;
+                uint32_t rb[LOG_R];
+#pragma unroll
+                for (int s = 0; s < LOG_R; ++s) {
+                    rb[s] = (regs >> (4 * s)) & 15u;
+                    regmask |= 1u << rb[s];
+                }
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    uint32_t o = 0;
+#pragma unroll
+                    for (int s = 0; s < LOG_R; ++s)
+                        if ((j >> s) & 1)
+                            o |= 1u << rb[s];
+                    offs[j] = o;
+                }
+                tbase = 0;
+                int tbit = 0;
+#pragma unroll
+                for (int b = 0; b < K; ++b) {
+                    if (!((regmask >> b) & 1u)) {
+                        tbase |= ((tid >> tbit) & 1u) << b;
+                        ++tbit;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    v[j] = lds[tbase | offs[j]];
+                __syncthreads();
+                have = true;
+                continue;
+            }
+            if ((base & op.hmask) != op.hmask)
+                continue;
+            const uint32_t cm = op.cmask;
+            if (kind == OP_U) {
+                Mat<R> m;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    m.a[i] = (R)op.m[i];
+                dispatch_u(op.slot, v, m, cm, tbase, offs);
+            } else if (kind == OP_X) {
+                dispatch_x(op.slot, v, cm, tbase, offs);
+            } else if (kind == OP_NEG) {
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const bool p = ((tbase | offs[j]) & cm) == cm;
+                    v[j].x = p ? -v[j].x : v[j].x;
+                    v[j].y = p ? -v[j].y : v[j].y;
+                }
+            } else if (kind == OP_DIAG) {
+                const R d0r = (R)op.m[0], d0i = (R)op.m[1], d1r = (R)op.m[2], d1i = (R)op.m[3];
+                const int tb = op.slot;
+                const bool hsel = (base & op.hbit) != 0;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const uint32_t idx = tbase | offs[j];
+                    const bool p = (idx & cm) == cm;
+                    const bool sel = tb >= 0 ? ((idx >> tb) & 1u) != 0 : hsel;
+                    const R dr = sel ? d1r : d0r, di = sel ? d1i : d0i;
+                    const C x = v[j];
+                    const R nr = dr * x.x - di * x.y, ni = dr * x.y + di * x.x;
+                    v[j].x = p ? nr : x.x;
+                    v[j].y = p ? ni : x.y;
+                }
+            }
+        }
+
+        if (have) {
+            if (a.has_perm) {
+                const uint32_t pt = bitperm(tbase, a.perm);
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    lds[pt | bitperm(offs[j], a.perm)] = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    lds[tbase | offs[j]] = v[j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                st[base + dtid + slot_offset(a, j)] = lds[j * NT + tid];
+        } else {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const uint32_t t = (uint32_t)(j * NT) + tid;
+                const uint32_t src = a.has_perm ? bitperm(t, a.pinv) : t;
+                st[base + dtid + slot_offset(a, j)] = lds[src];
+            }
+        }
+    }
+};
+
+template <typename R, int LOG_NT, int LOG_R>
+__global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    TileKernel<R, LOG_NT, LOG_R>::run(a, lds_raw);
+}
+
+template <typename R, int LOG_NT, int LOG_R>
+void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    constexpr size_t bytes = sizeof(C) << (LOG_NT + LOG_R);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess)
+            fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
+        attr_set = true;
+    }
+    if (n_tiles > 0x7fffffffull)
+        fail(QS_ERR_UNSUPPORTED, "too many tiles for one launch");
+    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)n_tiles), dim3(1 << LOG_NT), bytes, st, a);
+    check_launch("tile pass");
+}
+
+// Dispatch over the instantiated shapes: 2^6..2^10 threads, 2..32 amplitudes
+// per thread, tile bytes within the LDS of one CU.
+template <typename R>
+void launch_tile_t(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st)
+{
+#define QS_TILE_CASE(NTB, RB)                                          \
+    if (log_nt == NTB && log_r == RB) {                                \
+        if constexpr ((sizeof(typename Cx<R>::T) << (NTB + RB)) <= 131072) { \
+            launch_tile_inst<R, NTB, RB>(a, n_tiles, st);              \
+            return;                                                    \
+        }                                                              \
+    }
+#define QS_TILE_ROW(NTB) \
+    QS_TILE_CASE(NTB, 1) QS_TILE_CASE(NTB, 2) QS_TILE_CASE(NTB, 3) QS_TILE_CASE(NTB, 4) QS_TILE_CASE(NTB, 5)
+    QS_TILE_ROW(6)
+    QS_TILE_ROW(7)
+    QS_TILE_ROW(8)
+    QS_TILE_ROW(9)
+    QS_TILE_ROW(10)
+#undef QS_TILE_ROW
+#undef QS_TILE_CASE
+    fail(QS_ERR_UNSUPPORTED, "tile shape not instantiated (log_nt=" + std::to_string(log_nt) +
+                                 ", log_r=" + std::to_string(log_r) + ")");
+}
+
+}  // namespace qsim

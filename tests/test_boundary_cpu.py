@@ -1,0 +1,120 @@
+"""CPU checks of the C boundary: the library loads and exports every entry
+point the header declares, and the host-only compiler (the permutation pass of
+Section 3) matches the oracle pass instruction by instruction."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2010_09746_amd import qsim as Q
+from workloads import (config_circuit, layered_circuit, make_gates, mixed_circuit, paper_random_circuit,
+                       qft_like_circuit, KIND_CX, KIND_U, H)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "qsim.h")).read()
+    return sorted(set(re.findall(r"\b(qs_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(Q.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = Q.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_gate_record_layout():
+    assert Q.GATE_DTYPE.itemsize == 80
+    assert Q.GATE_DTYPE.fields["u"][1] == 16
+
+
+def _same_as_oracle(g, n, m, r=1, pinned=0):
+    ref, _ = O.pass_ref(g, n, m, r=r, pinned=pinned)
+    P = Q.Program(g, n, "c128", k_tile=m, max_swaps=r, pinned=pinned)
+    ins = P.instructions()
+    st = P.stats()
+    P.close()
+    assert ins == ref
+    return st
+
+
+@pytest.mark.parametrize("n,m,p,seed", [(8, 6, 0.3, 1), (12, 9, 0.0, 2), (16, 13, 1.0, 3), (20, 16, 0.3, 4),
+                                        (30, 24, 0.3, 5), (50, 40, 0.3, 6)])
+def test_pass_matches_oracle_paper_family(n, m, p, seed):
+    _same_as_oracle(paper_random_circuit(n, 30 * n, p, seed), n, m)
+
+
+@pytest.mark.parametrize("n,m,seed", [(7, 3, 1), (9, 5, 2), (12, 7, 3)])
+def test_pass_matches_oracle_all_gate_kinds(n, m, seed):
+    _same_as_oracle(mixed_circuit(n, 150, seed), n, m)
+
+
+@pytest.mark.parametrize("r,pinned", [(2, 0), (4, 3), (8, 3), (1, 3)])
+def test_pass_extensions_match_oracle(r, pinned):
+    _same_as_oracle(layered_circuit(16, 12, seed=9), 16, 10, r=r, pinned=pinned)
+
+
+def test_pass_matches_oracle_layered_config_shape():
+    # the 30-qubit, 40-layer circuit shape at tile size 12
+    st = _same_as_oracle(config_circuit(2), 30, 12)
+    assert st["n_gates"] == 1800 and st["n_global"] == 0
+
+
+def test_pass_matches_oracle_qft_like():
+    for n in (10, 20, 30):
+        _same_as_oracle(qft_like_circuit(n), n, n - n // 5)
+
+
+def test_program_stats_consistent():
+    g = config_circuit(2)
+    P = Q.Program(g, 30, "c128", k_tile=12, max_swaps=4)
+    s = P.stats()
+    assert s["n_apply"] + s["n_global"] == 1800
+    assert s["n_tile_passes"] >= s["n_perm"]
+    assert s["n_move_passes"] == s["n_perm"]
+    P2 = Q.Program(g, 30, "c128", k_tile=12, max_swaps=4, perm_exec="relabel")
+    assert P2.instructions() == P.instructions()
+    assert P2.stats()["n_move_passes"] == 0
+    plain = Q.Program(g, 30, "c128", form="plain")
+    assert plain.stats()["n_plain"] == 1800
+
+
+def test_compile_rejects_bad_input():
+    g = make_gates([(KIND_CX, 0, 0, None)])
+    with pytest.raises(Q.QsimError) as e:
+        Q.Program(g, 4, "c128")
+    assert e.value.code == -1
+    g = make_gates([(KIND_U, 5, -1, H)])
+    with pytest.raises(Q.QsimError):
+        Q.Program(g, 4, "c128")
+    with pytest.raises(Q.QsimError):
+        Q.Program(make_gates([(KIND_U, 0, -1, H)]), 4, "c128", sigma0=[0, 1, 1, 2])
+    with pytest.raises(Q.QsimError):
+        Q.Program(make_gates([(KIND_U, 0, -1, H)]), 4, "c128", max_swaps=0)
+    bad = make_gates([(KIND_U, 0, -1, H)])
+    bad[0]["kind"] = 9
+    with pytest.raises(Q.QsimError):
+        Q.Program(bad, 4, "c128")
+
+
+def test_compile_with_start_placement():
+    n = 10
+    g = mixed_circuit(n, 80, seed=5)
+    sigma0 = list(np.random.default_rng(2).permutation(n))
+    P = Q.Program(g, n, "c128", sigma0=sigma0, k_tile=7)
+    ins = P.instructions()
+    v, sig = O.run_program(g, n, ins, sigma0=sigma0)
+    assert np.abs(O.to_logical(v, n, sig) - O.run(g, n)).max() < 1e-13
+
+
+def test_empty_circuit_compiles():
+    P = Q.Program(np.zeros(0, dtype=Q.GATE_DTYPE), 8, "c64")
+    assert P.stats()["n_gates"] == 0 and P.instructions() == []
