@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--dtype", default="c128")
-    ap.add_argument("--k", type=int, default=12)
+    ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--perm-exec", default="relabel")
     ap.add_argument("--pinned", type=int, default=3)

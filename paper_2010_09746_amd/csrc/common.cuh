@@ -44,6 +44,26 @@ template <typename R> struct Mat {
         r.y = a[4] * x.y + a[5] * x.x + a[6] * y.y + a[7] * y.x;
         return r;
     }
+    // (x, y) <- (m00 x + m01 y, m10 x + m11 y), updated in place.  The terms
+    // in x are summed first, so x is dead before the new x is written and only
+    // one value needs a temporary.
+    template <typename C> __device__ __forceinline__ void apply(C &x, C &y) const
+    {
+        R t0 = a[0] * x.x, t1 = a[0] * x.y, t2 = a[4] * x.x, t3 = a[4] * x.y;
+        t0 = __builtin_fma(-a[1], x.y, t0);
+        t1 = __builtin_fma(a[1], x.x, t1);
+        t2 = __builtin_fma(-a[5], x.y, t2);
+        t3 = __builtin_fma(a[5], x.x, t3);
+        t0 = __builtin_fma(a[2], y.x, t0);
+        t1 = __builtin_fma(a[2], y.y, t1);
+        t2 = __builtin_fma(a[6], y.x, t2);
+        t3 = __builtin_fma(a[6], y.y, t3);
+        x.x = __builtin_fma(-a[3], y.y, t0);
+        x.y = __builtin_fma(a[3], y.x, t1);
+        const R ny = __builtin_fma(-a[7], y.y, t2);
+        y.y = __builtin_fma(a[7], y.x, t3);
+        y.x = ny;
+    }
 };
 
 inline void check_launch(const char *what)

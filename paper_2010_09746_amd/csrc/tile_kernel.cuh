@@ -35,36 +35,38 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return ((jj >> S) << (S + 1)) | (jj & ((1 << S) - 1));
     }
 
+    // dense 2x2 on slot S, in place; with CTRL only where the tile-local index
+    // matches: (idx & cm) == cv
     template <int S, bool CTRL>
-    static __device__ __forceinline__ void bfly(C (&v)[NR], const Mat<R> &m, uint32_t cm, uint32_t tbase,
+    static __device__ __forceinline__ void bfly(C (&v)[NR], const Mat<R> &m, uint32_t cm, uint32_t cv, uint32_t tbase,
                                                 const uint32_t (&offs)[NR])
     {
 #pragma unroll
         for (int jj = 0; jj < NR / 2; ++jj) {
             const int j = pair_lo<S>(jj), j1 = j | (1 << S);
-            const C x = v[j], y = v[j1];
-            const C nx = m.row0(x, y), ny = m.row1(x, y);
             if (CTRL) {
-                const bool p = ((tbase | offs[j]) & cm) == cm;
-                v[j].x = p ? nx.x : x.x;
-                v[j].y = p ? nx.y : x.y;
-                v[j1].x = p ? ny.x : y.x;
-                v[j1].y = p ? ny.y : y.y;
+                C x = v[j], y = v[j1];
+                m.apply(x, y);
+                const bool p = ((tbase | offs[j]) & cm) == cv;
+                v[j].x = p ? x.x : v[j].x;
+                v[j].y = p ? x.y : v[j].y;
+                v[j1].x = p ? y.x : v[j1].x;
+                v[j1].y = p ? y.y : v[j1].y;
             } else {
-                v[j] = nx;
-                v[j1] = ny;
+                m.apply(v[j], v[j1]);
             }
         }
     }
 
     template <int S>
-    static __device__ __forceinline__ void xswap(C (&v)[NR], uint32_t cm, uint32_t tbase, const uint32_t (&offs)[NR])
+    static __device__ __forceinline__ void xswap(C (&v)[NR], uint32_t cm, uint32_t cv, uint32_t tbase,
+                                                 const uint32_t (&offs)[NR])
     {
 #pragma unroll
         for (int jj = 0; jj < NR / 2; ++jj) {
             const int j = pair_lo<S>(jj), j1 = j | (1 << S);
             const C x = v[j], y = v[j1];
-            const bool p = ((tbase | offs[j]) & cm) == cm;
+            const bool p = ((tbase | offs[j]) & cm) == cv;
             v[j].x = p ? y.x : x.x;
             v[j].y = p ? y.y : x.y;
             v[j1].x = p ? x.x : y.x;
@@ -73,30 +75,30 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     }
 
     template <int S = 0>
-    static __device__ __forceinline__ void dispatch_u(int slot, C (&v)[NR], const Mat<R> &m, uint32_t cm,
+    static __device__ __forceinline__ void dispatch_u(int slot, C (&v)[NR], const Mat<R> &m, uint32_t cm, uint32_t cv,
                                                       uint32_t tbase, const uint32_t (&offs)[NR])
     {
         if constexpr (S < LOG_R) {
             if (slot == S) {
                 if (cm == 0)
-                    bfly<S, false>(v, m, cm, tbase, offs);
+                    bfly<S, false>(v, m, cm, cv, tbase, offs);
                 else
-                    bfly<S, true>(v, m, cm, tbase, offs);
+                    bfly<S, true>(v, m, cm, cv, tbase, offs);
             } else {
-                dispatch_u<S + 1>(slot, v, m, cm, tbase, offs);
+                dispatch_u<S + 1>(slot, v, m, cm, cv, tbase, offs);
             }
         }
     }
 
     template <int S = 0>
-    static __device__ __forceinline__ void dispatch_x(int slot, C (&v)[NR], uint32_t cm, uint32_t tbase,
+    static __device__ __forceinline__ void dispatch_x(int slot, C (&v)[NR], uint32_t cm, uint32_t cv, uint32_t tbase,
                                                       const uint32_t (&offs)[NR])
     {
         if constexpr (S < LOG_R) {
             if (slot == S)
-                xswap<S>(v, cm, tbase, offs);
+                xswap<S>(v, cm, cv, tbase, offs);
             else
-                dispatch_x<S + 1>(slot, v, cm, tbase, offs);
+                dispatch_x<S + 1>(slot, v, cm, cv, tbase, offs);
         }
     }
 
@@ -120,13 +122,40 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return dj;
     }
 
+    using OpPtr = const __attribute__((address_space(4))) TileOp *;
+
+    // the fields of one operation, held in scalar registers
+    struct OpV {
+        int32_t kind, slot;
+        uint32_t cmask, regs;
+        uint64_t hmask, hbit;
+        double m[8];
+    };
+
+    static __device__ __forceinline__ OpV fetch(OpPtr ops, int i)
+    {
+        OpV o;
+        o.kind = ops[i].kind;
+        o.slot = ops[i].slot;
+        o.cmask = ops[i].cmask;
+        o.regs = ops[i].regs;
+        o.hmask = ops[i].hmask;
+        o.hbit = ops[i].hbit;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            o.m[q] = ops[i].m[q];
+        return o;
+    }
+
+    // Register slot j holds the amplitude of register pattern j ^ fl: an
+    // exchange (X) whose control is the same for the whole tile flips a bit of
+    // fl instead of moving data.  F is fl deposited into tile bits, so the
+    // tile-local index of slot j is (tbase | offs[j]) ^ F.
     static __device__ __forceinline__ void run(const TileArgs &a, unsigned char *lds_raw)
     {
         C *lds = reinterpret_cast<C *>(lds_raw);
         C *st = reinterpret_cast<C *>(a.state);
-        // operations are read with uniform (scalar) loads
-        const __attribute__((address_space(4))) TileOp *ops =
-            (const __attribute__((address_space(4))) TileOp *)(a.ops);
+        OpPtr ops = (OpPtr)(a.ops);
         const uint32_t tid = threadIdx.x;
 
         // base index: the tile number with a zero inserted at every tile position
@@ -155,20 +184,26 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
 #pragma unroll
         for (int j = 0; j < NR; ++j)
             offs[j] = 0;
-        uint32_t tbase = 0;
+        uint32_t tbase = 0, regs = 0, fl = 0, F = 0;
         bool have = false;
 
-        for (int oi = 0; oi < a.n_ops; ++oi) {
-            const __attribute__((address_space(4))) TileOp &op = ops[oi];
-            const int kind = op.kind;
+        const int n_ops = a.n_ops;
+        OpV cur;
+        if (n_ops > 0)
+            cur = fetch(ops, 0);
+        for (int oi = 0; oi < n_ops; ++oi) {
+            OpV nxt;
+            if (oi + 1 < n_ops)
+                nxt = fetch(ops, oi + 1);
+            const int kind = cur.kind;
             if (kind == OP_REMAP) {
                 if (have) {
 #pragma unroll
                     for (int j = 0; j < NR; ++j)
-                        lds[tbase | offs[j]] = v[j];
+                        lds[(tbase | offs[j]) ^ F] = v[j];
                     __syncthreads();
                 }
-                const uint32_t regs = op.regs;
+                regs = cur.regs;
                 uint32_t regmask = 0;
                 uint32_t rb[LOG_R];
 #pragma unroll
@@ -198,55 +233,68 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 for (int j = 0; j < NR; ++j)
                     v[j] = lds[tbase | offs[j]];
                 __syncthreads();
+                fl = 0;
+                F = 0;
                 have = true;
-                continue;
-            }
-            if ((base & op.hmask) != op.hmask)
-                continue;
-            const uint32_t cm = op.cmask;
-            if (kind == OP_U) {
-                Mat<R> m;
+            } else if ((base & cur.hmask) == cur.hmask) {
+                const uint32_t cm = cur.cmask;
+                const uint32_t cv = cm & ~F;  // (idx ^ F) & cm == cm  <=>  idx & cm == cm & ~F
+                if (kind == OP_U) {
+                    Mat<R> m;
+                    const bool sw = (fl >> cur.slot) & 1u;
+                    // with the slot's pattern bit flipped, rows and columns trade places
+                    m.a[0] = (R)(sw ? cur.m[6] : cur.m[0]);
+                    m.a[1] = (R)(sw ? cur.m[7] : cur.m[1]);
+                    m.a[2] = (R)(sw ? cur.m[4] : cur.m[2]);
+                    m.a[3] = (R)(sw ? cur.m[5] : cur.m[3]);
+                    m.a[4] = (R)(sw ? cur.m[2] : cur.m[4]);
+                    m.a[5] = (R)(sw ? cur.m[3] : cur.m[5]);
+                    m.a[6] = (R)(sw ? cur.m[0] : cur.m[6]);
+                    m.a[7] = (R)(sw ? cur.m[1] : cur.m[7]);
+                    dispatch_u(cur.slot, v, m, cm, cv, tbase, offs);
+                } else if (kind == OP_X) {
+                    if (cm == 0) {
+                        fl ^= 1u << cur.slot;
+                        F ^= 1u << ((regs >> (4 * cur.slot)) & 15u);
+                    } else {
+                        dispatch_x(cur.slot, v, cm, cv, tbase, offs);
+                    }
+                } else if (kind == OP_NEG) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    m.a[i] = (R)op.m[i];
-                dispatch_u(op.slot, v, m, cm, tbase, offs);
-            } else if (kind == OP_X) {
-                dispatch_x(op.slot, v, cm, tbase, offs);
-            } else if (kind == OP_NEG) {
+                    for (int j = 0; j < NR; ++j) {
+                        const bool p = ((tbase | offs[j]) & cm) == cv;
+                        v[j].x = p ? -v[j].x : v[j].x;
+                        v[j].y = p ? -v[j].y : v[j].y;
+                    }
+                } else {  // OP_DIAG
+                    const R d0r = (R)cur.m[0], d0i = (R)cur.m[1], d1r = (R)cur.m[2], d1i = (R)cur.m[3];
+                    const int tb = cur.slot;
+                    const bool hsel = (base & cur.hbit) != 0;
 #pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    const bool p = ((tbase | offs[j]) & cm) == cm;
-                    v[j].x = p ? -v[j].x : v[j].x;
-                    v[j].y = p ? -v[j].y : v[j].y;
+                    for (int j = 0; j < NR; ++j) {
+                        const uint32_t idx = (tbase | offs[j]) ^ F;
+                        const bool p = (idx & cm) == cm;
+                        const bool sel = tb >= 0 ? ((idx >> tb) & 1u) != 0 : hsel;
+                        const R dr = sel ? d1r : d0r, di = sel ? d1i : d0i;
+                        const C x = v[j];
+                        const R nr = dr * x.x - di * x.y, ni = dr * x.y + di * x.x;
+                        v[j].x = p ? nr : x.x;
+                        v[j].y = p ? ni : x.y;
+                    }
                 }
-            } else if (kind == OP_DIAG) {
-                const R d0r = (R)op.m[0], d0i = (R)op.m[1], d1r = (R)op.m[2], d1i = (R)op.m[3];
-                const int tb = op.slot;
-                const bool hsel = (base & op.hbit) != 0;
-#pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    const uint32_t idx = tbase | offs[j];
-                    const bool p = (idx & cm) == cm;
-                    const bool sel = tb >= 0 ? ((idx >> tb) & 1u) != 0 : hsel;
-                    const R dr = sel ? d1r : d0r, di = sel ? d1i : d0i;
-                    const C x = v[j];
-                    const R nr = dr * x.x - di * x.y, ni = dr * x.y + di * x.x;
-                    v[j].x = p ? nr : x.x;
-                    v[j].y = p ? ni : x.y;
-                }
             }
+            cur = nxt;
         }
 
         if (have) {
             if (a.has_perm) {
-                const uint32_t pt = bitperm(tbase, a.perm);
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    lds[pt | bitperm(offs[j], a.perm)] = v[j];
+                    lds[bitperm((tbase | offs[j]) ^ F, a.perm)] = v[j];
             } else {
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    lds[tbase | offs[j]] = v[j];
+                    lds[(tbase | offs[j]) ^ F] = v[j];
             }
             __syncthreads();
 #pragma unroll
