@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "tile_pass_traffic.json"))
+    ap.add_argument("--form", default="pass", choices=["pass", "precision", "batch"],
+                    help="pass: the 30-qubit complex128 workload (default line); precision: 32 qubits, complex64 "
+                         "against complex128")
     return ap.parse_args()
 
 
@@ -70,11 +73,116 @@ def cpu_baseline(gates, n, seconds):
                 sample=f"first {done} gates of the same {n}-qubit circuit, complex128, {dt:.1f} s")
 
 
+def precision(a):
+    """32 qubits, 50 layers: the pass form in complex64 and in complex128 on
+    the same circuit; per-result error of complex64 against complex128 (FP64
+    read-out on both)."""
+    import numpy as np
+    import torch
+
+    from paper_2010_09746_amd import qsim as Q
+    from workloads import config_samples, layered_circuit, MASTER_SEED
+
+    n = a.n if a.n != 30 else 32
+    layers = a.layers if a.layers != 40 else 50
+    gates = layered_circuit(n, layers, MASTER_SEED + 3, cz_every_third=True)
+    samples = config_samples(3, n=n)
+    upd = len(gates) * float(1 << n)
+    out = {}
+    states = {}
+    for dt, k in (("c64", a.k + 1), ("c128", a.k)):
+        st = Q.State(n, dt)
+        opts = dict(form="pass", k_tile=k, max_swaps=a.r, perm_exec="relabel", pinned=a.pinned)
+        st.run(gates, **opts)  # warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(1, a.steps)):
+            t0 = time.perf_counter()
+            st.set_basis(0)
+            st.run(gates, **opts)
+            z = st.expect_z()
+            amp = st.amplitudes(samples)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = float(np.median(ts))
+        out[dt] = dict(ms_per_step=ms * 1e3, value=upd / ms, k_tile=k, norm=st.norm())
+        states[dt] = (st, z, amp)
+        print(f"{dt}: {ms * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    loss, mx = states["c64"][0].fidelity(states["c128"][0])
+    err = dict(fidelity_loss=loss, max_abs_amp=mx,
+               max_abs_expect_z=float(np.abs(states["c64"][1] - states["c128"][1]).max()),
+               max_abs_sampled_amp=float(np.abs(states["c64"][2] - states["c128"][2]).max()),
+               norm_c64_minus_1=states["c64"][0].norm() - 1.0, norm_c128_minus_1=states["c128"][0].norm() - 1.0)
+    line = {
+        "metric": "amplitude-updates/s", "value": out["c64"]["value"], "unit": "amplitude-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": 1, "ms_per_step": out["c64"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"precision form: random circuit n={n}, {layers} layers ({len(gates)} gates), complex64 "
+                               f"bulk with FP64 read-out vs complex128", "parallelism": "1 GPU"},
+        "c64": out["c64"], "c128": out["c128"], "c64_vs_c128": err,
+        "tolerance": {"fidelity_loss": 1e-6, "max_abs_amp": 1e-5},
+        "within_tolerance": bool(loss <= 1e-6 and mx <= 1e-5),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def batch(a):
+    """256 seeded circuits, n uniform in [10, 24], depth uniform in [10, 60],
+    complex64: one persistent launch per run, replayed from a HIP graph, with
+    k and the fusion depth chosen by the autotuner."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2010_09746_amd import autotune, qsim as Q
+    from workloads import batch_workload
+
+    wl = batch_workload(count=256)
+    circuits = [(n, g) for n, d, g in wl]
+    t0 = time.perf_counter()
+    best, table = autotune.tune_batch(circuits, "c64", reps=2,
+                                      log=lambda m: print("tune " + m, file=sys.stderr, flush=True))
+    tune_s = time.perf_counter() - t0
+    b = Q.Batch(circuits, "c64", **best)
+    b.run()
+    b.results()
+    ts = []
+    for _ in range(max(1, a.steps)):
+        t1 = time.perf_counter()
+        b.run()
+        z, nrm = b.results()
+        ts.append(time.perf_counter() - t1)
+    sec = float(np.median(ts))
+    st = b.stats()
+    upd = sum(len(g) * float(1 << n) for n, g in circuits)
+    # accuracy: oracle on every circuit of at most 16 qubits
+    errs = [abs(z[c] - O.expect_z(O.run(g, n), n)[0]) for c, (n, g) in enumerate(circuits) if n <= 16]
+    b.close()
+    line = {
+        "metric": "amplitude-updates/s", "value": upd / sec, "unit": "amplitude-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batching form: 256 seeded layered circuits, n uniform in [10,24], depth uniform in "
+                               "[10,60], complex64; one persistent launch under a HIP graph; output <Z_0> and norm "
+                               "per circuit", "parallelism": "1 GPU"},
+        "circuits_per_s": len(circuits) / sec,
+        "tuned": best, "tune_seconds": tune_s, "tune_candidates": len(table),
+        "batch_stats": st,
+        "max_norm_error": float(np.abs(nrm - 1).max()),
+        "oracle_checked_circuits": len(errs), "max_abs_z0_error_vs_oracle": float(max(errs) if errs else 0.0),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if a.form == "precision":
+        return precision(a)
+    if a.form == "batch":
+        return batch(a)
 
     import numpy as np
     import torch

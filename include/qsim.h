@@ -195,6 +195,56 @@ qs_status qs_fidelity(qs_state *a, qs_state *b, double *loss, double *max_abs_di
 /* Wait for all work enqueued on the state's stream. */
 qs_status qs_synchronize(qs_state *s);
 
+/* ---- batching form ---------------------------------------------------------- */
+
+/* Options of a batch.
+ *   k_tile     tile qubits, shared by every circuit (7 <= k_tile <= every n)
+ *   max_swaps  r of the pass (see qs_run_opts); placements are relabelled
+ *   pinned     positions never exchanged out (see qs_run_opts)
+ *   reg_bits   amplitudes per thread = 2^reg_bits (0 = library choice)
+ *   max_fuse   gates per tile pass bound (0 = none)
+ *   wg_per_cu  workgroups per compute unit of each level launch
+ *   chunk      tiles per work item
+ *   use_graph  1: capture the launch sequence once in a HIP graph and replay it */
+typedef struct {
+    int32_t k_tile;
+    int32_t max_swaps;
+    int32_t pinned;
+    int32_t reg_bits;
+    int32_t max_fuse;
+    int32_t wg_per_cu;
+    int32_t chunk;
+    int32_t use_graph;
+} qs_batch_opts;
+
+typedef struct {
+    int64_t n_gates, n_perm, n_passes, n_tiles, n_items;
+    double state_bytes, compile_ms;
+} qs_batch_stats;
+
+/* Compile count circuits (circuit c: n_qubits[c] qubits, gates[c] a host array
+ * of n_gates[c] gates) for execution together.  Circuits advance one pass
+ * level at a time: level L holds every circuit's L-th tile pass, and one
+ * persistent launch strides over the tiles of a level.  The library allocates
+ * one device buffer holding every state (complex64 or complex128), the
+ * compiled pass tables and its own HIP stream.  Compilation runs on host
+ * threads. */
+qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *gates, const int64_t *n_gates,
+                          qs_dtype dt, const qs_batch_opts *opts, qs_batch **out);
+/* Enqueue one execution: every state set to |0...0>, one persistent launch per
+ * pass level, then the per-circuit read-out.  With use_graph the whole
+ * sequence is captured in a HIP graph on the first call and replayed after. */
+qs_status qs_batch_run(qs_batch *b);
+/* Wait for the last run; z0[c] = <Z_0> and norms[c] = sum |a|^2 of circuit c
+ * (host arrays of count doubles, FP64 accumulation; either may be NULL). */
+qs_status qs_batch_results(qs_batch *b, double *z0, double *norms);
+/* Amplitudes of one circuit (n <= 26) in logical order into out (host,
+ * 2^(n+1) doubles); call after qs_batch_results. */
+qs_status qs_batch_read_state(qs_batch *b, int circuit, double *out);
+qs_status qs_batch_get_stats(const qs_batch *b, qs_batch_stats *out);
+qs_status qs_batch_synchronize(qs_batch *b);
+qs_status qs_batch_destroy(qs_batch *b);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Per kernel class: launches recorded, summed device time between HIP events

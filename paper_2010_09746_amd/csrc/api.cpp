@@ -40,11 +40,15 @@ namespace qsim {
 
 [[noreturn]] void fail(qs_status code, const std::string &msg) { throw Error{code, msg}; }
 
+namespace {
+thread_local std::string g_err;
+}
+
+void set_last_error(const std::string &msg) { g_err = msg; }
+
 }  // namespace qsim
 
 namespace {
-
-thread_local std::string g_err;
 
 template <typename F> qs_status guard(F &&f)
 {

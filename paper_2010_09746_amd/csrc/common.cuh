@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "internal.h"
@@ -18,6 +19,10 @@ template <typename R> struct alignas(2 * sizeof(R)) Cplx {
 template <typename R> struct Cx {
     using T = Cplx<R>;
 };
+
+// fused multiply-add in the amplitude's own precision
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // 2x2 complex matrix, row-major (u00, u01, u10, u11) as re/im pairs.
 template <typename R> struct Mat {
@@ -50,18 +55,18 @@ template <typename R> struct Mat {
     template <typename C> __device__ __forceinline__ void apply(C &x, C &y) const
     {
         R t0 = a[0] * x.x, t1 = a[0] * x.y, t2 = a[4] * x.x, t3 = a[4] * x.y;
-        t0 = __builtin_fma(-a[1], x.y, t0);
-        t1 = __builtin_fma(a[1], x.x, t1);
-        t2 = __builtin_fma(-a[5], x.y, t2);
-        t3 = __builtin_fma(a[5], x.x, t3);
-        t0 = __builtin_fma(a[2], y.x, t0);
-        t1 = __builtin_fma(a[2], y.y, t1);
-        t2 = __builtin_fma(a[6], y.x, t2);
-        t3 = __builtin_fma(a[6], y.y, t3);
-        x.x = __builtin_fma(-a[3], y.y, t0);
-        x.y = __builtin_fma(a[3], y.x, t1);
-        const R ny = __builtin_fma(-a[7], y.y, t2);
-        y.y = __builtin_fma(a[7], y.x, t3);
+        t0 = fmadd(-a[1], x.y, t0);
+        t1 = fmadd(a[1], x.x, t1);
+        t2 = fmadd(-a[5], x.y, t2);
+        t3 = fmadd(a[5], x.x, t3);
+        t0 = fmadd(a[2], y.x, t0);
+        t1 = fmadd(a[2], y.y, t1);
+        t2 = fmadd(a[6], y.x, t2);
+        t3 = fmadd(a[6], y.y, t3);
+        x.x = fmadd(-a[3], y.y, t0);
+        x.y = fmadd(a[3], y.x, t1);
+        const R ny = fmadd(-a[7], y.y, t2);
+        y.y = fmadd(a[7], y.x, t3);
         y.x = ny;
     }
 };

@@ -74,6 +74,33 @@ struct TileArgs {
 };
 
 // ---------------------------------------------------------------------------
+// batching form: one persistent launch over many circuits
+
+// One tile pass of one circuit of a batch (device memory).
+struct BatchPass {
+    TileArgs t;       // the circuit's state, this pass's ops and tile positions
+    uint32_t ntiles;  // tiles of this pass = 2^(n - k)
+    int32_t last;     // 1: write read-out partials after the pass
+    int32_t zpos;     // physical position of qubit 0
+    int32_t pad;
+    uint64_t part;    // first read-out partial (two doubles per tile) of the circuit
+};
+
+// A range of tiles of one pass: the unit of work of a level launch.
+struct BatchItem {
+    uint32_t pass, t0, t1, pad;
+};
+
+// One level: every circuit's pass of that index; the items of a level are
+// independent of each other, and levels run in launch order.
+struct BatchArgs {
+    const BatchPass *passes;
+    const BatchItem *items;
+    uint32_t i0, i1;       // items of this level
+    double *partials;
+};
+
+// ---------------------------------------------------------------------------
 // compiled program
 
 enum LaunchType : int { L_TILE = 0, L_PLAIN = 1, L_MOVE = 2 };
@@ -133,5 +160,7 @@ struct Error {
     std::string msg;
 };
 [[noreturn]] void fail(qs_status code, const std::string &msg);
+// message returned by qs_last_error() on this thread
+void set_last_error(const std::string &msg);
 
 }  // namespace qsim

@@ -24,6 +24,16 @@ void launch_involution(void *state, qs_dtype dt, int n, const std::vector<int> &
 void launch_tile_f32(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st);
 void launch_tile_f64(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st);
 
+// Batching form.  All states |0> (element offsets of each circuit's first
+// amplitude in starts_dev), one persistent launch per pass level, then the
+// per-circuit read-out out_dev[2c] = <Z_0>, out_dev[2c+1] = norm.
+void launch_batch_init(void *state, qs_dtype dt, uint64_t total_elems, const uint64_t *starts_dev, int count,
+                       hipStream_t st);
+void launch_batch_f32(const BatchArgs &b, int log_r, int log_nt, int grid, hipStream_t st);
+void launch_batch_f64(const BatchArgs &b, int log_r, int log_nt, int grid, hipStream_t st);
+void launch_batch_reduce(const double *partials, const uint64_t *part_off, const uint32_t *part_cnt, int count,
+                         double *out, hipStream_t st);
+
 // Read-out: norm and position sums S_p = sum_j |v_j|^2 bit_p(j), written to
 // out_dev[0] (norm) and out_dev[1 + p].  work_dev holds the block partials.
 size_t zsum_work_doubles(int n);

@@ -102,7 +102,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         }
     }
 
-    static __device__ __forceinline__ uint32_t bitperm(uint32_t x, const uint8_t *perm)
+    template <typename P> static __device__ __forceinline__ uint32_t bitperm(uint32_t x, P perm)
     {
         uint32_t y = 0;
 #pragma unroll
@@ -112,7 +112,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     }
 
     // deposit of the tile's register-slot bits j into the positions pos[LOG_NT..K)
-    static __device__ __forceinline__ uint64_t slot_offset(const TileArgs &a, int j)
+    template <typename A> static __device__ __forceinline__ uint64_t slot_offset(const A &a, int j)
     {
         uint64_t dj = 0;
 #pragma unroll
@@ -151,7 +151,18 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     // exchange (X) whose control is the same for the whole tile flips a bit of
     // fl instead of moving data.  F is fl deposited into tile bits, so the
     // tile-local index of slot j is (tbase | offs[j]) ^ F.
-    static __device__ __forceinline__ void run(const TileArgs &a, unsigned char *lds_raw)
+    // Per-tile read-out of the final amplitudes: sum |a|^2 and sum |a|^2 (1 - 2 b)
+    // where b is the bit at physical position zpos (the first qubit), reduced
+    // over the workgroup in a fixed order and written to out[0..1].
+    struct Readout {
+        double *out;  // NULL: none
+        int zpos;
+    };
+
+    // One tile.  A is TileArgs, read from kernel arguments or from device
+    // memory; tile is the tile number (index over the positions outside it).
+    template <typename A>
+    static __device__ __forceinline__ void run(const A &a, unsigned char *lds_raw, uint64_t tile, Readout ro)
     {
         C *lds = reinterpret_cast<C *>(lds_raw);
         C *st = reinterpret_cast<C *>(a.state);
@@ -160,7 +171,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
 
         // base index: the tile number with a zero inserted at every tile position
         // (positions ascending)
-        uint64_t base = blockIdx.x;
+        uint64_t base = tile;
 #pragma unroll
         for (int b = 0; b < K; ++b) {
             const int p = a.pos[b];
@@ -188,13 +199,8 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         bool have = false;
 
         const int n_ops = a.n_ops;
-        OpV cur;
-        if (n_ops > 0)
-            cur = fetch(ops, 0);
         for (int oi = 0; oi < n_ops; ++oi) {
-            OpV nxt;
-            if (oi + 1 < n_ops)
-                nxt = fetch(ops, oi + 1);
+            const OpV cur = fetch(ops, oi);
             const int kind = cur.kind;
             if (kind == OP_REMAP) {
                 if (have) {
@@ -283,7 +289,6 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                     }
                 }
             }
-            cur = nxt;
         }
 
         if (have) {
@@ -299,14 +304,50 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-                st[base + dtid + slot_offset(a, j)] = lds[j * NT + tid];
+                v[j] = lds[j * NT + tid];
         } else {
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
                 const uint32_t t = (uint32_t)(j * NT) + tid;
                 const uint32_t src = a.has_perm ? bitperm(t, a.pinv) : t;
-                st[base + dtid + slot_offset(a, j)] = lds[src];
+                v[j] = lds[src];
             }
+        }
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            st[base + dtid + slot_offset(a, j)] = v[j];
+        if (ro.out)
+            readout(a, v, base, dtid, ro, reinterpret_cast<double *>(lds_raw));
+    }
+
+    template <typename A>
+    static __device__ __forceinline__ void readout(const A &a, const C (&v)[NR], uint64_t base, uint64_t dtid,
+                                                   Readout ro, double *red)
+    {
+        const uint32_t tid = threadIdx.x;
+        double nrm = 0.0, z = 0.0;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const uint64_t phys = base + dtid + slot_offset(a, j);
+            const double re = (double)v[j].x, im = (double)v[j].y, p = re * re + im * im;
+            nrm += p;
+            z += ((phys >> ro.zpos) & 1ull) ? -p : p;
+        }
+        __syncthreads();  // the tile buffer is reused for the reduction
+        red[tid] = nrm;
+        red[NT + tid] = z;
+        __syncthreads();
+#pragma unroll
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if ((int)tid < w) {
+                red[tid] += red[tid + w];
+                red[NT + tid] += red[NT + tid + w];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            ro.out[0] = red[0];
+            ro.out[1] = red[NT];
         }
     }
 };
@@ -315,7 +356,7 @@ template <typename R, int LOG_NT, int LOG_R>
 __global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    TileKernel<R, LOG_NT, LOG_R>::run(a, lds_raw);
+    TileKernel<R, LOG_NT, LOG_R>::run(a, lds_raw, blockIdx.x, {nullptr, 0});
 }
 
 template <typename R, int LOG_NT, int LOG_R>
@@ -323,7 +364,8 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
 {
     using C = typename Cx<R>::T;
     constexpr size_t bytes = sizeof(C) << (LOG_NT + LOG_R);
-    static bool attr_set = false;
+    // launches above the default dynamic LDS limit need the attribute first
+    static bool attr_set = bytes <= 65536;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

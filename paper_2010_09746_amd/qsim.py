@@ -42,6 +42,8 @@ EXPORTS = [
     "qs_permute_qubits", "qs_compile", "qs_program_destroy", "qs_program_get_stats",
     "qs_program_instructions", "qs_run_program", "qs_run_circuit", "qs_read_amplitudes", "qs_read_state",
     "qs_expect_z", "qs_norm", "qs_fidelity", "qs_synchronize", "qs_profile_enable", "qs_profile_read",
+    "qs_batch_create", "qs_batch_run", "qs_batch_results", "qs_batch_read_state", "qs_batch_get_stats",
+    "qs_batch_synchronize", "qs_batch_destroy",
 ]
 
 
@@ -61,6 +63,18 @@ class qs_program_stats(ctypes.Structure):
     _fields_ = [("n_gates", ctypes.c_int64), ("n_apply", ctypes.c_int64), ("n_perm", ctypes.c_int64),
                 ("n_global", ctypes.c_int64), ("n_swaps", ctypes.c_int64), ("n_tile_passes", ctypes.c_int64),
                 ("n_move_passes", ctypes.c_int64), ("n_plain", ctypes.c_int64), ("n_remaps", ctypes.c_int64),
+                ("compile_ms", ctypes.c_double)]
+
+
+class qs_batch_opts(ctypes.Structure):
+    _fields_ = [("k_tile", ctypes.c_int32), ("max_swaps", ctypes.c_int32), ("pinned", ctypes.c_int32),
+                ("reg_bits", ctypes.c_int32), ("max_fuse", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class qs_batch_stats(ctypes.Structure):
+    _fields_ = [("n_gates", ctypes.c_int64), ("n_perm", ctypes.c_int64), ("n_passes", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("n_items", ctypes.c_int64), ("state_bytes", ctypes.c_double),
                 ("compile_ms", ctypes.c_double)]
 
 
@@ -107,6 +121,14 @@ def load() -> ctypes.CDLL:
     L.qs_norm.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
     L.qs_fidelity.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.qs_synchronize.argtypes = [_vp]
+    L.qs_batch_create.argtypes = [ctypes.c_int, _ip, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.c_int, ctypes.POINTER(qs_batch_opts), ctypes.POINTER(_vp)]
+    L.qs_batch_run.argtypes = [_vp]
+    L.qs_batch_results.argtypes = [_vp, _vp, _vp]
+    L.qs_batch_read_state.argtypes = [_vp, ctypes.c_int, _vp]
+    L.qs_batch_get_stats.argtypes = [_vp, ctypes.POINTER(qs_batch_stats)]
+    L.qs_batch_synchronize.argtypes = [_vp]
+    L.qs_batch_destroy.argtypes = [_vp]
     L.qs_profile_enable.argtypes = [ctypes.c_int]
     L.qs_profile_read.argtypes = [ctypes.POINTER(qs_profile_entry), ctypes.c_int, _ip]
     for name in EXPORTS:
@@ -308,6 +330,58 @@ def qs_profile_read() -> dict:
     return out
 
 
+def make_batch_opts(k_tile=10, max_swaps=8, pinned=3, reg_bits=0, max_fuse=0, wg_per_cu=8, chunk=8,
+                    use_graph=1) -> qs_batch_opts:
+    o = qs_batch_opts()
+    o.k_tile, o.max_swaps, o.pinned, o.reg_bits = k_tile, max_swaps, pinned, reg_bits
+    o.max_fuse, o.wg_per_cu, o.chunk, o.use_graph = max_fuse, wg_per_cu, chunk, use_graph
+    return o
+
+
+def qs_batch_create(circuits, dtype, opts: qs_batch_opts) -> int:
+    """circuits: sequence of (n, gates)."""
+    arrs = [as_gates(g) for _, g in circuits]
+    cnt = len(arrs)
+    ns = np.ascontiguousarray([int(n) for n, _ in circuits], dtype=np.intc)
+    ptrs = (ctypes.c_void_p * cnt)(*[a.ctypes.data for a in arrs])
+    ngs = (ctypes.c_int64 * cnt)(*[len(a) for a in arrs])
+    h = _vp()
+    _chk(load().qs_batch_create(cnt, ns.ctypes.data_as(_ip), ptrs, ngs, _dtype_code(dtype), ctypes.byref(opts),
+                                ctypes.byref(h)))
+    return h.value
+
+
+def qs_batch_run(h: int) -> None:
+    _chk(load().qs_batch_run(h))
+
+
+def qs_batch_results(h: int, count: int):
+    z = np.zeros(count, dtype=np.float64)
+    nrm = np.zeros(count, dtype=np.float64)
+    _chk(load().qs_batch_results(h, z.ctypes.data, nrm.ctypes.data))
+    return z, nrm
+
+
+def qs_batch_read_state(h: int, c: int, n: int) -> np.ndarray:
+    out = np.zeros(2 << n, dtype=np.float64)
+    _chk(load().qs_batch_read_state(h, c, out.ctypes.data))
+    return out[0::2] + 1j * out[1::2]
+
+
+def qs_batch_get_stats(h: int) -> dict:
+    st = qs_batch_stats()
+    _chk(load().qs_batch_get_stats(h, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in qs_batch_stats._fields_}
+
+
+def qs_batch_synchronize(h: int) -> None:
+    _chk(load().qs_batch_synchronize(h))
+
+
+def qs_batch_destroy(h: int) -> None:
+    _chk(load().qs_batch_destroy(h))
+
+
 # ---------------------------------------------------------------------------
 # owners
 
@@ -406,6 +480,44 @@ class Program:
     def close(self):
         if getattr(self, "h", None):
             qs_program_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many circuits (list of (n, gates)) run by one persistent launch."""
+
+    def __init__(self, circuits, dtype="c64", **opts):
+        self.ns = [int(n) for n, _ in circuits]
+        self.count = len(self.ns)
+        self.opts = dict(opts)
+        self.h = qs_batch_create(circuits, dtype, make_batch_opts(**opts))
+
+    def run(self) -> "Batch":
+        qs_batch_run(self.h)
+        return self
+
+    def results(self):
+        """(<Z_0>, norm) per circuit after the last run."""
+        return qs_batch_results(self.h, self.count)
+
+    def state(self, c: int) -> np.ndarray:
+        return qs_batch_read_state(self.h, c, self.ns[c])
+
+    def stats(self) -> dict:
+        return qs_batch_get_stats(self.h)
+
+    def synchronize(self) -> None:
+        qs_batch_synchronize(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            qs_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -246,3 +246,35 @@ def test_config2_full_size_pass_vs_plain():
     assert abs(na - 1) <= 1e-12
     assert np.abs(amp_a - amp_b).max() <= 1e-12
     assert np.abs(za - zb).max() <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# precision form: complex64 bulk with FP64 read-out against complex128
+
+
+@pytest.mark.parametrize("n,layers", [(20, 50), (24, 12)])
+def test_precision_c64_vs_c128(n, layers):
+    _say(f"precision c64 vs c128 n={n} layers={layers}")
+    g = layered_circuit(n, layers, seed=20100949)
+    a = Q.State(n, "c64").run(g, form="pass", k_tile=11, max_swaps=8, perm_exec="relabel", pinned=4)
+    b = Q.State(n, "c128").run(g, form="pass", k_tile=10, max_swaps=8, perm_exec="relabel", pinned=3)
+    loss, mx = a.fidelity(b)
+    assert loss <= 1e-6 and mx <= 1e-5, (loss, mx)
+    assert np.abs(a.expect_z() - b.expect_z()).max() <= 1e-5
+    assert abs(a.norm() - 1) <= 1e-5
+    if n <= 20:
+        ref = O.run(g, n)
+        assert np.abs(b.to_numpy() - ref).max() <= 1e-12
+
+
+def test_precision_c128_oracle_28_qubits():
+    """The complex128 path that serves as the reference of the precision form,
+    checked against the oracle at 28 qubits (3 layers: the oracle's cost)."""
+    n = 28
+    _say("c128 vs oracle at 28 qubits")
+    g = layered_circuit(n, 3, seed=20100949)
+    ref = O.run(g, n)
+    idx = np.sort(np.random.default_rng(3).choice(1 << n, 4096, replace=False)).astype(np.uint64)
+    st = Q.State(n, "c128").run(g, form="pass", k_tile=10, max_swaps=8, perm_exec="relabel", pinned=3)
+    assert np.abs(st.amplitudes(idx) - ref[idx.astype(np.int64)]).max() <= 1e-12
+    assert np.abs(st.expect_z() - O.expect_z(ref, n)).max() <= 1e-12
