@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "tile_pass_traffic.json"))
-    ap.add_argument("--form", default="pass", choices=["pass", "precision", "batch"],
+    ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
+    ap.add_argument("--form", default="pass", choices=["pass", "precision", "batch", "serve"],
                     help="pass: the 30-qubit complex128 workload (default line); precision: 32 qubits, complex64 "
                          "against complex128")
     return ap.parse_args()
@@ -174,6 +176,44 @@ def batch(a):
     print(json.dumps(line), flush=True)
 
 
+def serve(a):
+    """Seeded Poisson trace (rate, count), n uniform in [12, 30], depth uniform
+    in [20, 100], complex64 with FP64 reductions, 200 GB budget, states
+    resident; each request returns <Z_q> for all q and 16 sampled amplitudes."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2010_09746_amd.serving import Server, latency_summary
+    from workloads import layered_circuit, request_trace
+
+    trace = request_trace(count=a.requests, rate=a.rate)
+    reqs = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in trace]
+    srv = Server("c64", k_tile=10, max_swaps=16, pinned=3, reg_bits=3, hbm_budget=200e9, max_slots=256)
+    # warm-up: one small request outside the measured trace
+    srv.serve([dict(id=-1, arrival=0.0, n=12, gates=layered_circuit(12, 4, 1), samples=[0])], realtime=False)
+    res, rec = srv.serve(reqs, realtime=True, log=lambda m: print("serve " + m, file=sys.stderr, flush=True))
+    st = latency_summary(rec)
+    errs = []
+    for r in reqs:
+        if r["n"] <= 18:
+            ref = O.run(r["gates"], r["n"])
+            errs.append(max(float(np.abs(res[r["id"]]["z"] - O.expect_z(ref, r["n"])).max()),
+                            float(np.abs(res[r["id"]]["amps"] - ref[np.asarray(r["samples"], dtype=np.int64)]).max())))
+    line = {
+        "metric": "served p50/p99 latency", "value": st["p99_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": st["makespan_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving form: Poisson trace {a.requests} requests at {a.rate}/s, n uniform in "
+                               f"[12,30], depth uniform in [20,100], complex64 with FP64 reductions, 200 GB budget, "
+                               f"<Z_q> all q + 16 sampled amplitudes per request", "parallelism": "1 GPU"},
+        "latency": st, "server": srv.last_stats,
+        "accuracy": {"oracle_checked_requests": len(errs), "max_abs_error": max(errs) if errs else None,
+                     "tolerance": 1e-5},
+    }
+    srv.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -183,6 +223,8 @@ def main():
         return precision(a)
     if a.form == "batch":
         return batch(a)
+    if a.form == "serve":
+        return serve(a)
 
     import numpy as np
     import torch

@@ -39,6 +39,7 @@ extern "C" {
 typedef struct qs_state qs_state;
 typedef struct qs_program qs_program;
 typedef struct qs_batch qs_batch;
+typedef struct qs_server qs_server;
 
 typedef enum {
     QS_C64 = 0,  /* complex64: float re, im (8 bytes per amplitude)  */
@@ -244,6 +245,43 @@ qs_status qs_batch_read_state(qs_batch *b, int circuit, double *out);
 qs_status qs_batch_get_stats(const qs_batch *b, qs_batch_stats *out);
 qs_status qs_batch_synchronize(qs_batch *b);
 qs_status qs_batch_destroy(qs_batch *b);
+
+/* ---- serving form ------------------------------------------------------------ */
+
+/* A server keeps admitted requests' states resident and advances them by
+ * continuous batching: every step is one launch that runs the next tile pass
+ * of every resident request; requests join at step boundaries and leave when
+ * their last pass has run and their read-out is copied to the host.
+ *   dt, opts     amplitude type and pass options shared by all requests
+ *                (opts->use_graph is ignored)
+ *   hbm_budget   bytes of request states that may be resident at once
+ *   max_slots    resident requests at once (1..4096)
+ *   max_samples  sampled amplitudes per request (read-out)
+ * The server allocates its own stream, a device arena for pass tables, tile
+ * operations and read-outs, and pinned host buffers for results. */
+qs_status qs_server_create(qs_dtype dt, const qs_batch_opts *opts, size_t hbm_budget, int max_slots,
+                           int max_samples, qs_server **out);
+qs_status qs_server_destroy(qs_server *s);
+/* 1 in *fits if a state of n qubits can be admitted now (budget and slots). */
+qs_status qs_server_fits(const qs_server *s, int n, int *fits);
+/* Admit a compiled program (compiled for this server's dt with
+ * QS_PERM_RELABEL, k_tile = opts->k_tile, identity start placement).
+ * state_buf: caller-owned device buffer of 2^n amplitudes (not freed by the
+ * server; it must stay valid until qs_server_release).  samples: count
+ * logical basis indices (host) whose amplitudes are returned.  Fails with
+ * QS_ERR_BUDGET when the budget or the slots are exhausted. */
+qs_status qs_server_admit(qs_server *s, const qs_program *p, void *state_buf, size_t buf_bytes,
+                          const uint64_t *samples, int count, int64_t *request_id);
+/* Enqueue one step; *n_running receives the requests advanced. */
+qs_status qs_server_step_launch(qs_server *s, int *n_running);
+/* Wait for the last step; writes the ids of requests that completed in it
+ * (up to cap) into ids and their number into *n_done. */
+qs_status qs_server_step_wait(qs_server *s, int64_t *ids, int cap, int *n_done);
+/* Results of a completed request: z (host, n doubles) = <Z_q>, amps (host,
+ * 2*count doubles, interleaved re, im) and *norm, all accumulated in FP64. */
+qs_status qs_server_result(qs_server *s, int64_t request_id, double *z, double *amps, double *norm);
+/* Forget a completed request (its state buffer may then be reused). */
+qs_status qs_server_release(qs_server *s, int64_t request_id);
 
 /* ---- measurement ---------------------------------------------------------- */
 

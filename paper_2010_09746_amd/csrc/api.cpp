@@ -32,10 +32,6 @@ struct qs_state {
     int64_t idx_cap = 0;
 };
 
-struct qs_program {
-    Program p;
-};
-
 namespace qsim {
 
 [[noreturn]] void fail(qs_status code, const std::string &msg) { throw Error{code, msg}; }

@@ -149,6 +149,15 @@ struct Program {
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0,
                      const qs_run_opts &o, Program &p);
 
+}  // namespace qsim
+
+// handle behind qs_program
+struct qs_program {
+    qsim::Program p;
+};
+
+namespace qsim {
+
 // choose register bits / threads for a tile of k bits
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);
 

@@ -44,6 +44,8 @@ EXPORTS = [
     "qs_expect_z", "qs_norm", "qs_fidelity", "qs_synchronize", "qs_profile_enable", "qs_profile_read",
     "qs_batch_create", "qs_batch_run", "qs_batch_results", "qs_batch_read_state", "qs_batch_get_stats",
     "qs_batch_synchronize", "qs_batch_destroy",
+    "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
+    "qs_server_step_wait", "qs_server_result", "qs_server_release",
 ]
 
 
@@ -129,6 +131,16 @@ def load() -> ctypes.CDLL:
     L.qs_batch_get_stats.argtypes = [_vp, ctypes.POINTER(qs_batch_stats)]
     L.qs_batch_synchronize.argtypes = [_vp]
     L.qs_batch_destroy.argtypes = [_vp]
+    L.qs_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(qs_batch_opts), ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_int, ctypes.POINTER(_vp)]
+    L.qs_server_destroy.argtypes = [_vp]
+    L.qs_server_fits.argtypes = [_vp, ctypes.c_int, _ip]
+    L.qs_server_admit.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int64)]
+    L.qs_server_step_launch.argtypes = [_vp, _ip]
+    L.qs_server_step_wait.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _ip]
+    L.qs_server_result.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
+    L.qs_server_release.argtypes = [_vp, ctypes.c_int64]
     L.qs_profile_enable.argtypes = [ctypes.c_int]
     L.qs_profile_read.argtypes = [ctypes.POINTER(qs_profile_entry), ctypes.c_int, _ip]
     for name in EXPORTS:
@@ -380,6 +392,57 @@ def qs_batch_synchronize(h: int) -> None:
 
 def qs_batch_destroy(h: int) -> None:
     _chk(load().qs_batch_destroy(h))
+
+
+def qs_server_create(dtype, opts: qs_batch_opts, hbm_budget: int, max_slots: int, max_samples: int) -> int:
+    h = _vp()
+    _chk(load().qs_server_create(_dtype_code(dtype), ctypes.byref(opts), int(hbm_budget), max_slots, max_samples,
+                                 ctypes.byref(h)))
+    return h.value
+
+
+def qs_server_destroy(h: int) -> None:
+    _chk(load().qs_server_destroy(h))
+
+
+def qs_server_fits(h: int, n: int) -> bool:
+    f = ctypes.c_int()
+    _chk(load().qs_server_fits(h, n, ctypes.byref(f)))
+    return bool(f.value)
+
+
+def qs_server_admit(h: int, prog: int, buf_ptr: int, buf_bytes: int, samples) -> int:
+    smp = np.ascontiguousarray(np.asarray(samples, dtype=np.uint64))
+    rid = ctypes.c_int64()
+    _chk(load().qs_server_admit(h, prog, buf_ptr, buf_bytes, smp.ctypes.data if len(smp) else None, len(smp),
+                                ctypes.byref(rid)))
+    return rid.value
+
+
+def qs_server_step_launch(h: int) -> int:
+    n = ctypes.c_int()
+    _chk(load().qs_server_step_launch(h, ctypes.byref(n)))
+    return n.value
+
+
+def qs_server_step_wait(h: int, cap: int = 4096):
+    ids = (ctypes.c_int64 * cap)()
+    n = ctypes.c_int()
+    _chk(load().qs_server_step_wait(h, ids, cap, ctypes.byref(n)))
+    return [ids[i] for i in range(min(n.value, cap))]
+
+
+def qs_server_result(h: int, rid: int, n: int, count: int):
+    z = np.zeros(n, dtype=np.float64)
+    amps = np.zeros(2 * max(count, 1), dtype=np.float64)
+    nrm = ctypes.c_double()
+    _chk(load().qs_server_result(h, rid, z.ctypes.data, amps.ctypes.data, ctypes.byref(nrm)))
+    a = amps[0:2 * count:2] + 1j * amps[1:2 * count:2]
+    return z, a, nrm.value
+
+
+def qs_server_release(h: int, rid: int) -> None:
+    _chk(load().qs_server_release(h, rid))
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,91 @@
+"""Serving form: continuous batching of resident requests.  Each request's
+results are the same alone and in the mix (complex64 tolerance), and match the
+oracle; the memory budget bounds what is resident."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import layered_circuit, request_trace, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2010_09746_amd import qsim as Q  # noqa: E402
+from paper_2010_09746_amd.serving import Server, latency_summary  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(count, n_lo, n_hi, d_lo, d_hi, seed, spacing=0.0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        d = int(rng.integers(d_lo, d_hi + 1))
+        out.append(dict(id=i, arrival=i * spacing, n=n, gates=layered_circuit(n, d, seed=seed * 1000 + i),
+                        samples=sample_indices(n, 16, seed * 1000 + i)))
+    return out
+
+
+def test_results_same_alone_and_in_the_mix():
+    _say("serving: mix vs alone")
+    reqs = _requests(24, 12, 17, 3, 10, seed=3)
+    srv = Server("c64", k_tile=10, max_swaps=8, pinned=3, reg_bits=3, max_slots=64)
+    res, rec = srv.serve(reqs, realtime=False)
+    assert srv.last_stats["max_resident"] > 1  # work did overlap
+    for r in reqs:
+        n, g = r["n"], r["gates"]
+        st = Q.State(n, "c64").run(g, form="pass", k_tile=10, max_swaps=8, pinned=3, perm_exec="relabel",
+                                   reg_bits=3)
+        alone_z, alone_a = st.expect_z(), st.amplitudes(r["samples"])
+        mix = res[r["id"]]
+        assert np.abs(mix["z"] - alone_z).max() <= 1e-6
+        assert np.abs(mix["amps"] - alone_a).max() <= 1e-6
+        ref = O.run(g, n)
+        assert np.abs(mix["z"] - O.expect_z(ref, n)).max() <= 1e-5
+        assert np.abs(mix["amps"] - ref[np.asarray(r["samples"], dtype=np.int64)]).max() <= 1e-5
+        assert abs(mix["norm"] - 1) <= 1e-5
+        st.close()
+    srv.close()
+
+
+def test_budget_bounds_resident_states():
+    _say("serving: budget")
+    reqs = _requests(10, 16, 16, 4, 6, seed=4)
+    budget = 2 * (8 << 16)  # two 16-qubit complex64 states
+    srv = Server("c64", k_tile=10, max_swaps=8, hbm_budget=budget, max_slots=8)
+    res, rec = srv.serve(reqs, realtime=False)
+    assert srv.last_stats["max_resident"] <= 2
+    assert len(res) == len(reqs)
+    # a state beyond the budget is refused with QS_ERR_BUDGET
+    assert not Q.qs_server_fits(srv.h, 18)
+    big = torch.empty(8 << 17, dtype=torch.uint8, device="cuda")
+    p = srv.compile(layered_circuit(17, 2, seed=1), 17)
+    with pytest.raises(Q.QsimError) as e:
+        for _ in range(3):
+            Q.qs_server_admit(srv.h, p.h, big.data_ptr(), big.numel(), [])
+    assert e.value.code == -3
+    srv.close()
+
+
+def test_realtime_trace_latencies():
+    _say("serving: realtime trace")
+    trace = request_trace(count=40, rate=400.0, n_lo=12, n_hi=18, d_lo=5, d_hi=12)
+    reqs = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in trace]
+    srv = Server("c64", k_tile=10, max_swaps=16, max_slots=32)
+    res, rec = srv.serve(reqs, realtime=True)
+    s = latency_summary(rec)
+    assert s["requests"] == 40 and 0 < s["p50_s"] <= s["p99_s"]
+    for r in reqs[::7]:
+        ref = O.run(r["gates"], r["n"])
+        assert np.abs(res[r["id"]]["z"] - O.expect_z(ref, r["n"])).max() <= 1e-5
+    srv.close()

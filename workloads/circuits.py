@@ -92,20 +92,48 @@ def haar_u2(rng: np.random.Generator) -> np.ndarray:
         dtype=np.complex128)
 
 
+def _haar_batch(rng: np.random.Generator, count: int) -> np.ndarray:
+    """``count`` Haar-random U(2) matrices (same parametrisation as haar_u2),
+    as a (count, 2, 2) complex array."""
+    a, p, c = (rng.uniform(0.0, 2.0 * math.pi, size=count) for _ in range(3))
+    f = np.arcsin(np.sqrt(rng.uniform(0.0, 1.0, size=count)))
+    ph = np.exp(1j * a)
+    m = np.empty((count, 2, 2), dtype=np.complex128)
+    m[:, 0, 0] = ph * np.exp(1j * p) * np.cos(f)
+    m[:, 0, 1] = ph * np.exp(1j * c) * np.sin(f)
+    m[:, 1, 0] = -ph * np.exp(-1j * c) * np.sin(f)
+    m[:, 1, 1] = ph * np.exp(-1j * p) * np.cos(f)
+    return m
+
+
 def layered_circuit(n: int, layers: int, seed: int, cz_every_third: bool = True) -> np.ndarray:
     """Haar-U(2) on every qubit, then a 2q gate on each pair of a random perfect
     matching (control = first of the pair; odd n leaves the last qubit idle).
     With ``cz_every_third`` the 2q gate is CZ on layers l with l % 3 == 2."""
     rng = _rng(seed, n, layers)
-    recs = []
+    per = n + n // 2
+    g = np.zeros(layers * per, dtype=GATE_DTYPE)
+    x_mat, z_mat = _pack(X), _pack(Z)
     for layer in range(layers):
-        for q in range(n):
-            recs.append((KIND_U, q, -1, haar_u2(rng)))
+        base = layer * per
+        mats = _haar_batch(rng, n)
+        blk = g[base:base + n]
+        blk["kind"] = KIND_U
+        blk["q0"] = np.arange(n)
+        blk["q1"] = -1
+        u = mats.reshape(n, 4)
+        blk["u"][:, 0::2] = u.real
+        blk["u"][:, 1::2] = u.imag
+        g[base:base + n] = blk
         perm = rng.permutation(n)
-        kind = KIND_CZ if (cz_every_third and layer % 3 == 2) else KIND_CX
-        for i in range(0, n - 1, 2):
-            recs.append((kind, int(perm[i]), int(perm[i + 1]), None))
-    return make_gates(recs)
+        two = g[base + n:base + per]
+        cz = cz_every_third and layer % 3 == 2
+        two["kind"] = KIND_CZ if cz else KIND_CX
+        two["q0"] = perm[0:2 * (n // 2):2]
+        two["q1"] = perm[1:2 * (n // 2):2]
+        two["u"] = z_mat if cz else x_mat
+        g[base + n:base + per] = two
+    return g
 
 
 def paper_random_circuit(n: int, n_gates: int, p: float, seed: int) -> np.ndarray:
