@@ -45,12 +45,26 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "tile_pass_traffic.json"))
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many GiB 3 times (a plain copy kernel of "
+                         "known size, used to scale hardware byte counters)")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--form", default="pass", choices=["pass", "precision", "batch", "serve"],
                     help="pass: the 30-qubit complex128 workload (default line); precision: 32 qubits, complex64 "
                          "against complex128")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """sha1 of the tile kernel sources (hardware counters are stored with it)."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in ("tile_kernel.cuh", "common.cuh", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2010_09746_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def cpu_baseline(gates, n, seconds):
@@ -284,6 +298,14 @@ def main():
                               for k, v in prof_plain.items()})
         print(f"plain form: {ms_plain * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
 
+    if a.copy_calib > 0:
+        src = torch.ones(a.copy_calib << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     tile = prof_pass.get("tile_pass")
     roofline = None
     if tile:
@@ -294,7 +316,9 @@ def main():
             try:
                 tj = json.load(open(a.traffic_json))
                 key = f"n{n}_{dt}_k{a.k}_r{a.r}_{a.perm_exec}"
-                traffic = tj.get(key)
+                # counters only describe the kernel they were taken on
+                if tj.get("kernel_source_sha1") == kernel_source_hash():
+                    traffic = tj.get("bytes_per_launch", {}).get(key)
             except Exception:
                 traffic = None
         roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
