@@ -32,6 +32,13 @@ HIP_FLAGS = [
     # keep the per-slot branches of the tile kernel separate, so register
     # arrays are indexed with constants and stay in VGPRs
     "-mllvm", "-simplifycfg-sink-common=false",
+    # Branches on uniform values (operation kind, register slot, register
+    # controls) stay plain scalar branches instead of being rewritten into a
+    # structured form, and FP64 multiply-adds use the three-address form: with
+    # both, every variant of the tile kernel's op loop updates the register
+    # array in place instead of copying it at each iteration.
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
+    "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
@@ -40,7 +47,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "in
 
 def _run(cmd):
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l and "fmacf64-inst" not in l)
     if p.returncode != 0:
         raise RuntimeError("build step failed: " + " ".join(cmd) + "\n" + out)
     return out

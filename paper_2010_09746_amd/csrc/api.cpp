@@ -283,13 +283,10 @@ void run_launches(qs_state *s, Program &p)
             break;
         case L_TILE: {
             TileArgs a{};
+            tile_args_from_launch(L, a);
             a.state = s->buf;
             a.ops = p.d_ops + L.op_begin;
-            a.n_ops = L.op_count;
             a.n_hi = s->n - L.k;
-            for (int b = 0; b < L.k; ++b)
-                a.pos[b] = (uint8_t)L.pos[b];
-            a.has_perm = 0;
             const uint64_t tiles = 1ull << (s->n - L.k);
             timed(s->stream, P_TILE, 2.0 * (double)s->bytes, [&] {
                 if (s->dt == QS_C64)

@@ -208,18 +208,13 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
                     BatchPass P{};
                     P.t.state = static_cast<char *>(b->d_state) + b->start[c] * eb;
                     if (!tl.empty()) {
+                        tile_args_from_launch(*tl[i], P.t);
                         P.t.ops = b->d_ops + op_base + tl[i]->op_begin;
-                        P.t.n_ops = tl[i]->op_count;
-                        for (int q = 0; q < K; ++q)
-                            P.t.pos[q] = (uint8_t)tl[i]->pos[q];
                     } else {
+                        tile_args_identity(K, b->log_nt, b->log_r, P.t);
                         P.t.ops = b->d_ops;
-                        P.t.n_ops = 0;
-                        for (int q = 0; q < K; ++q)
-                            P.t.pos[q] = (uint8_t)q;
                     }
                     P.t.n_hi = b->n[c] - K;
-                    P.t.has_perm = 0;
                     P.ntiles = (uint32_t)ntiles;
                     P.last = i == np - 1;
                     P.zpos = p.sigma_final[0];

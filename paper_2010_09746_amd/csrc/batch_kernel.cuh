@@ -22,11 +22,8 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_batch(BatchArgs b)
     for (uint32_t it = b.i0 + blockIdx.x; it < b.i1; it += gridDim.x) {
         const uint32_t pi = items[it].pass, t0 = items[it].t0, t1 = items[it].t1;
         const auto &P = passes[pi];
-        for (uint32_t t = t0; t < t1; ++t) {
-            typename TK::Readout ro{P.last ? b.partials + 2 * (P.part + t) : nullptr, P.zpos};
-            TK::run(P.t, lds_raw, t, ro);
-            __syncthreads();
-        }
+        typename TK::Readout ro{P.last ? b.partials + 2 * (P.part + t0) : nullptr, P.zpos};
+        TK::template run_range<false>(P.t, lds_raw, t0, t1, 1, ro);
     }
 }
 

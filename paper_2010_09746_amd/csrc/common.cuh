@@ -49,25 +49,25 @@ template <typename R> struct Mat {
         r.y = a[4] * x.y + a[5] * x.x + a[6] * y.y + a[7] * y.x;
         return r;
     }
-    // (x, y) <- (m00 x + m01 y, m10 x + m11 y), updated in place.  The terms
-    // in x are summed first, so x is dead before the new x is written and only
-    // one value needs a temporary.
+    // (x, y) <- (m00 x + m01 y, m10 x + m11 y), updated in place.  Each output
+    // first sums the three terms that do not read its own old value; the
+    // last term reads the output's own register, so every result lands where
+    // its input was and no copies are needed.
     template <typename C> __device__ __forceinline__ void apply(C &x, C &y) const
     {
-        R t0 = a[0] * x.x, t1 = a[0] * x.y, t2 = a[4] * x.x, t3 = a[4] * x.y;
-        t0 = fmadd(-a[1], x.y, t0);
-        t1 = fmadd(a[1], x.x, t1);
-        t2 = fmadd(-a[5], x.y, t2);
-        t3 = fmadd(a[5], x.x, t3);
-        t0 = fmadd(a[2], y.x, t0);
-        t1 = fmadd(a[2], y.y, t1);
-        t2 = fmadd(a[6], y.x, t2);
-        t3 = fmadd(a[6], y.y, t3);
-        x.x = fmadd(-a[3], y.y, t0);
-        x.y = fmadd(a[3], y.x, t1);
-        const R ny = fmadd(-a[7], y.y, t2);
-        y.y = fmadd(a[7], y.x, t3);
-        y.x = ny;
+        R p0 = -a[1] * x.y, p1 = a[1] * x.x, p2 = a[4] * x.x, p3 = a[4] * x.y;
+        p0 = fmadd(a[2], y.x, p0);
+        p1 = fmadd(a[2], y.y, p1);
+        p2 = fmadd(-a[5], x.y, p2);
+        p3 = fmadd(a[5], x.x, p3);
+        p0 = fmadd(-a[3], y.y, p0);
+        p1 = fmadd(a[3], y.x, p1);
+        p2 = fmadd(-a[7], y.y, p2);
+        p3 = fmadd(a[7], y.x, p3);
+        x.x = fmadd(a[0], x.x, p0);
+        x.y = fmadd(a[0], x.y, p1);
+        y.x = fmadd(a[6], y.x, p2);
+        y.y = fmadd(a[6], y.y, p3);
     }
 };
 

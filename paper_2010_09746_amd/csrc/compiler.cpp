@@ -462,8 +462,26 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
                 }
                 TileOp op{};
                 op.kind = lg[v].kind;
-                op.slot = needs_reg(v) ? slot : lg[v].tb;
-                op.cmask = lg[v].cmask;
+                // split the in-tile controls into register slots and thread bits
+                for (int b = 0; b < k; ++b) {
+                    if (!((lg[v].cmask >> b) & 1u))
+                        continue;
+                    const int s = in_regs(b);
+                    if (s >= 0)
+                        op.rmask |= 1u << s;
+                    else
+                        op.lmask |= 1u << b;
+                }
+                if (needs_reg(v)) {
+                    op.slot = slot;
+                } else if (lg[v].kind == OP_DIAG) {
+                    const int tb = lg[v].tb;
+                    const int s = tb >= 0 ? in_regs(tb) : -1;
+                    op.slot = tb < 0 ? -2 : s >= 0 ? s : -1;
+                    op.tlane = tb >= 0 && s < 0 ? 1u << tb : 0u;
+                } else {
+                    op.slot = 0;
+                }
                 op.hmask = lg[v].hmask;
                 op.hbit = lg[v].hbit;
                 std::memcpy(op.m, lg[v].m, sizeof op.m);
@@ -499,7 +517,17 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
             regs[s] = want[s];
             packed |= (uint32_t)want[s] << (4 * s);
         }
-        op.regs = packed;
+        op.rmask = packed;
+        // thread-id bits take the other tile bits in ascending order
+        uint64_t lanes = 0;
+        for (int b = 0, i = 0; b < k; ++b) {
+            bool reg = false;
+            for (int s = 0; s < R; ++s)
+                reg |= regs[s] == b;
+            if (!reg)
+                lanes |= (uint64_t)b << (4 * i++);
+        }
+        op.hbit = lanes;
         ops.push_back(op);
         have = true;
         ++remaps;
@@ -507,7 +535,89 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
     return remaps;
 }
 
+// A tile is loaded straight into the layout of its first OP_REMAP (and stored
+// straight from its last one) when the thread bits of that layout include the
+// lowest tile bits, so that each load or store instruction still moves runs
+// of DIRECT_RUN_BYTES contiguous bytes.  Otherwise it is loaded (stored) in
+// tile-local index order j * NT + tid and goes through LDS.
+void set_direct_io(Launch &L, const std::vector<TileOp> &ops, qs_dtype dt)
+{
+    const int esize = dt == QS_C64 ? 8 : 16;
+    int low = 0;  // tile bits that must be thread bits
+    while ((esize << low) < DIRECT_RUN_BYTES)
+        ++low;
+    bool contiguous = true;
+    for (int b = 0; b < low && b < L.k; ++b)
+        contiguous &= L.pos[b] == b;
+    auto lanes_cover_low = [&](uint32_t regs) {
+        for (int s = 0; s < L.log_r; ++s)
+            if ((int)((regs >> (4 * s)) & 15u) < low)
+                return false;
+        return contiguous;
+    };
+    // positions of a layout given by packed register tile bits and lane map
+    auto layout = [&](uint32_t regs, uint64_t lanes, uint8_t *lane, uint8_t *reg) {
+        for (int i = 0; i < L.log_nt; ++i)
+            lane[i] = (uint8_t)L.pos[(lanes >> (4 * i)) & 15u];
+        for (int s = 0; s < L.log_r; ++s)
+            reg[s] = (uint8_t)L.pos[(regs >> (4 * s)) & 15u];
+    };
+    auto plain = [&](uint8_t *lane, uint8_t *reg) {
+        for (int i = 0; i < L.log_nt; ++i)
+            lane[i] = (uint8_t)L.pos[i];
+        for (int s = 0; s < L.log_r; ++s)
+            reg[s] = (uint8_t)L.pos[L.log_nt + s];
+    };
+    L.io = 0;
+    plain(L.ld_lane, L.ld_reg);
+    plain(L.st_lane, L.st_reg);
+    const TileOp *o = ops.data() + L.op_begin;
+    if (L.op_count == 0 || o[0].kind != OP_REMAP)
+        return;
+    if (lanes_cover_low(o[0].rmask)) {
+        L.io |= 1u;
+        layout(o[0].rmask, o[0].hbit, L.ld_lane, L.ld_reg);
+    }
+    for (int i = L.op_count - 1; i >= 0; --i)
+        if (o[i].kind == OP_REMAP) {
+            if (lanes_cover_low(o[i].rmask)) {
+                L.io |= 2u;
+                layout(o[i].rmask, o[i].hbit, L.st_lane, L.st_reg);
+            }
+            break;
+        }
+}
+
 }  // namespace
+
+void tile_args_from_launch(const Launch &L, TileArgs &a)
+{
+    a.n_ops = L.op_count;
+    for (int b = 0; b < 16; ++b)
+        a.pos[b] = (uint8_t)(b < L.k ? L.pos[b] : 0);
+    a.io = L.io;
+    for (int i = 0; i < 16; ++i) {
+        a.ld_lane[i] = L.ld_lane[i];
+        a.st_lane[i] = L.st_lane[i];
+    }
+    for (int s = 0; s < 8; ++s) {
+        a.ld_reg[s] = L.ld_reg[s];
+        a.st_reg[s] = L.st_reg[s];
+    }
+}
+
+void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a)
+{
+    Launch L;
+    L.type = L_TILE;
+    L.k = k;
+    L.log_nt = log_nt;
+    L.log_r = log_r;
+    for (int b = 0; b < k; ++b)
+        L.pos.push_back(b);
+    set_direct_io(L, {}, QS_C128);
+    tile_args_from_launch(L, a);
+}
 
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0_in,
                      const qs_run_opts &o, Program &p)
@@ -647,6 +757,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                 L.op_begin = (int)p.ops.size();
                 p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops);
                 L.op_count = (int)p.ops.size() - L.op_begin;
+                set_direct_io(L, p.ops, dt);
                 p.launches.push_back(L);
                 ++p.stats.n_tile_passes;
             }

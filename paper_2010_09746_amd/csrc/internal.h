@@ -35,43 +35,61 @@ bool gates_commute(const qs_gate &a, const GateInfo &ia, const qs_gate &b, const
 enum TileOpKind : int32_t {
     OP_U = 0,      // dense 2x2 on register slot `slot`
     OP_X = 1,      // exchange the pair on register slot `slot`
-    OP_DIAG = 2,   // multiply by d0 (m[0..1]) / d1 (m[2..3]) selected by a target bit
-    OP_NEG = 3,    // negate where all bits of cmask (tile) and hmask (outside) are 1
+    OP_DIAG = 2,   // multiply by d0 (m[0..1]) / d1 (m[2..3]) selected by the target bit
+    OP_NEG = 3,    // negate where every control bit is 1
     OP_REMAP = 4,  // move amplitudes through LDS to a new register layout
 };
 
-// One operation of a fused tile pass (96 bytes).  Control conditions: the
-// tile-local index must have every bit of cmask set and the tile's base
-// position every bit of hmask set.
+// One operation of a fused tile pass (104 bytes, every field at least 32 bits
+// wide and naturally aligned so that the kernel reads it with scalar loads).  Its controls are split by
+// where the control bit lives under the register layout in force when the
+// operation runs: register slots (rmask, a mask over slots), thread bits
+// (lmask, a mask over tile-local index bits) and positions outside the tile
+// (hmask, a mask over physical positions).  The operation acts where every
+// control bit is 1.
 struct TileOp {
     int32_t kind;
-    int32_t slot;      // OP_U/OP_X: register slot; OP_DIAG: tile bit of the target or -1
-    uint32_t cmask;
-    uint32_t regs;     // OP_REMAP: register tile bits, 4 bits each (slot s at bits 4s..4s+3)
+    int32_t slot;      // OP_U/OP_X: target register slot.  OP_DIAG: target
+                       // register slot, or -1 (target is the thread bit tlane)
+                       // or -2 (target outside the tile, at hbit)
+    uint32_t rmask;    // OP_REMAP: register tile bits, 4 bits each (slot s at bits 4s..4s+3)
+    uint32_t lmask;
+    uint32_t tlane;
+    uint32_t pad;
     uint64_t hmask;
-    uint64_t hbit;     // OP_DIAG with out-of-tile target: its position bit
+    uint64_t hbit;     // OP_DIAG target outside the tile; OP_REMAP: the tile bit of each
+                       // thread-id bit, 4 bits each (thread bit i at bits 4i..4i+3)
     double m[8];
 };
-static_assert(sizeof(TileOp) == 96, "TileOp layout");
+static_assert(sizeof(TileOp) == 104, "TileOp layout");
 
 constexpr int MAX_TILE_BITS = 15;
 constexpr int MIN_TILE_BITS = 7;
 constexpr int MAX_QUBITS = 34;          // states
 constexpr int MAX_COMPILE_QUBITS = 63;  // host-only compilation
 constexpr size_t MAX_TILE_BYTES = 131072;   // LDS of one tile (per workgroup)
+constexpr int DIRECT_RUN_BYTES = 128;       // contiguous bytes a direct tile load or store keeps together
 
-// Kernel arguments of one tile pass, passed by value.
+// Kernel arguments of one tile pass, passed by value.  The load and store
+// layouts give, for each thread-id bit and each register-slot bit, the
+// physical position it addresses.
 struct TileArgs {
     void *state;
     const TileOp *ops;
     int32_t n_ops;
     int32_t n_hi;                 // positions outside the tile
     uint8_t pos[16];              // tile bit b -> physical position (ascending)
-    uint8_t perm[16];             // store: tile bit b moves to tile bit perm[b]
-    uint8_t pinv[16];             // inverse of perm
-    int32_t has_perm;
+    uint8_t ld_lane[16];          // load layout: thread-id bit -> position
+    uint8_t ld_reg[8];            // load layout: slot bit -> position
+    uint8_t st_lane[16];          // store layout: thread-id bit -> position
+    uint8_t st_reg[8];            // store layout: slot bit -> position
+    uint32_t io;                  // bit 0: the load layout is that of ops[0] (an OP_REMAP, then
+                                  // skipped), else tile-local index j * NT + tid;
+                                  // bit 1: the store layout is that of the last OP_REMAP, else
+                                  // tile-local index j * NT + tid reached through LDS
     int32_t pad;
 };
+static_assert(sizeof(TileArgs) == 96, "TileArgs layout");
 
 // ---------------------------------------------------------------------------
 // batching form: one persistent launch over many circuits
@@ -111,7 +129,8 @@ struct Launch {
     int k = 0, log_r = 0, log_nt = 0;
     std::vector<int> pos;         // sorted tile positions
     int op_begin = 0, op_count = 0;
-    std::vector<int> perm;        // optional tile-bit permutation on store (empty = none)
+    uint32_t io = 0;              // TileArgs::io
+    uint8_t ld_lane[16] = {}, ld_reg[8] = {}, st_lane[16] = {}, st_reg[8] = {};  // TileArgs layouts
     // L_PLAIN
     qs_gate gate{};               // qubits already mapped to physical positions
     // L_MOVE
@@ -157,6 +176,12 @@ struct qs_program {
 };
 
 namespace qsim {
+
+// kernel arguments of a tile launch: op count, positions and load/store
+// layouts (the state and ops pointers and n_hi are the caller's)
+void tile_args_from_launch(const Launch &L, TileArgs &a);
+// kernel arguments of an empty tile pass over tile positions 0..k-1
+void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a);
 
 // choose register bits / threads for a tile of k bits
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);

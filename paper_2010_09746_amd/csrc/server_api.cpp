@@ -312,15 +312,11 @@ qs_status qs_server_admit(qs_server *s, const qs_program *pp, void *state_buf, s
             BatchPass P{};
             P.t.state = state_buf;
             if (!tl.empty()) {
+                tile_args_from_launch(*tl[i], P.t);
                 P.t.ops = d_ops + tl[i]->op_begin;
-                P.t.n_ops = tl[i]->op_count;
-                for (int q = 0; q < s->K; ++q)
-                    P.t.pos[q] = (uint8_t)tl[i]->pos[q];
             } else {
+                tile_args_identity(s->K, s->log_nt, s->log_r, P.t);
                 P.t.ops = d_ops;
-                P.t.n_ops = 0;
-                for (int q = 0; q < s->K; ++q)
-                    P.t.pos[q] = (uint8_t)q;
             }
             P.t.n_hi = n - s->K;
             P.ntiles = (uint32_t)ntiles;

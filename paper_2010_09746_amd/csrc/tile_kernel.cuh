@@ -1,22 +1,36 @@
-// Fused tile pass: one workgroup loads a tile of 2^K amplitudes, applies a run
-// of gates that act on the tile's qubits, and stores the tile back in place.
+// Fused tile pass: a workgroup takes tiles of 2^K amplitudes one after the
+// other, applies a run of gates that act on the tile's qubits to each, and
+// stores each tile back in place.
 //
 // The tile is the set of amplitudes whose physical index has fixed bits
 // outside K chosen positions pos[0..K) (the local qubits of the permutation
 // pass, paper, Section 3).  With pos = 0..K-1 the tile is a contiguous block;
 // when the pass only relabels qubits the tile gathers strided runs.
 //
+// Register layout: slot j of a thread holds the amplitude whose tile-local
+// index is tbase | off(j ^ fl).  off deposits the slot bits into the LOG_R
+// register tile bits chosen by the last OP_REMAP, tbase deposits the thread
+// id into the other tile bits, and fl records exchanges (X) that were the
+// same for the whole tile and were applied by relabelling slots instead of
+// moving data.
+//
 // Data path per tile:
-//   HBM -> LDS        coalesced: tile-local index t = j*NT + tid
-//   LDS -> registers  layout chosen per group of gates (OP_REMAP): the
-//                     register slots of a thread hold the 2^LOG_R amplitudes
-//                     whose tile-local indices differ in the LOG_R "register
-//                     bits"; the remaining bits come from the thread id
+//   HBM -> registers  straight into the layout of the first OP_REMAP when
+//                     the thread bits of that layout cover the lowest tile
+//                     bits (runs of at least 128 contiguous bytes); otherwise
+//                     into tile-local index j * NT + tid and through LDS
+//   LDS <-> registers each OP_REMAP writes the tile to LDS at its tile-local
+//                     indices and reads it back in the new layout
 //   gates             one-qubit updates and exchanges on register bits run
-//                     inside a thread; diagonal gates and controls on any bit
-//                     (or on a position outside the tile) are evaluated from
-//                     the tile-local index and the tile's base index
-//   registers -> LDS -> HBM  coalesced store
+//                     inside a thread.  A control on a register bit selects
+//                     register pairs by a test that is uniform over the
+//                     wavefront, a control on a thread bit selects per lane
+//                     without branching, and a control outside the tile
+//                     decides for the whole tile from its base index
+//   registers -> HBM  straight from the last layout when its thread bits
+//                     cover the lowest tile bits, else through LDS
+// While a tile is processed, the next tile of the workgroup is already being
+// loaded into a second register array.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +42,20 @@ namespace qsim {
 template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     using C = typename Cx<R>::T;
     static constexpr int NT = 1 << LOG_NT, NR = 1 << LOG_R, K = LOG_NT + LOG_R;
+    static constexpr uint32_t CB = sizeof(C);  // bytes per amplitude
+
+    // Order the LDS accesses of different lanes.  A single wavefront issues its
+    // LDS instructions in order, so only the compiler must be kept from
+    // reordering them; several wavefronts wait for their LDS operations and
+    // meet at a barrier.  Neither form waits for outstanding global loads, so
+    // the prefetch of the next tile stays in flight.
+    static __device__ __forceinline__ void lds_sync()
+    {
+        if constexpr (NT == 64)
+            __asm__ __volatile__("" ::: "memory");
+        else
+            __asm__ __volatile__("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    }
 
     // register slot pair (j, j | 2^S) for pair index jj
     template <int S> static constexpr int pair_lo(int jj)
@@ -35,110 +63,205 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return ((jj >> S) << (S + 1)) | (jj & ((1 << S) - 1));
     }
 
-    // dense 2x2 on slot S, in place; with CTRL only where the tile-local index
-    // matches: (idx & cm) == cv
-    template <int S, bool CTRL>
-    static __device__ __forceinline__ void bfly(C (&v)[NR], const Mat<R> &m, uint32_t cm, uint32_t cv, uint32_t tbase,
-                                                const uint32_t (&offs)[NR])
+    // dense 2x2 on slot S, in place, every pair.  With SW the slot's pattern
+    // bit is flipped (the upper slot of a pair holds pattern bit 0).
+    template <int S, bool SW> static __device__ __forceinline__ void bfly(C (&v)[NR], const Mat<R> &m)
     {
 #pragma unroll
         for (int jj = 0; jj < NR / 2; ++jj) {
             const int j = pair_lo<S>(jj), j1 = j | (1 << S);
-            if (CTRL) {
-                C x = v[j], y = v[j1];
-                m.apply(x, y);
-                const bool p = ((tbase | offs[j]) & cm) == cv;
-                v[j].x = p ? x.x : v[j].x;
-                v[j].y = p ? x.y : v[j].y;
-                v[j1].x = p ? y.x : v[j1].x;
-                v[j1].y = p ? y.y : v[j1].y;
-            } else {
-                m.apply(v[j], v[j1]);
-            }
-        }
-    }
-
-    template <int S>
-    static __device__ __forceinline__ void xswap(C (&v)[NR], uint32_t cm, uint32_t cv, uint32_t tbase,
-                                                 const uint32_t (&offs)[NR])
-    {
-#pragma unroll
-        for (int jj = 0; jj < NR / 2; ++jj) {
-            const int j = pair_lo<S>(jj), j1 = j | (1 << S);
-            const C x = v[j], y = v[j1];
-            const bool p = ((tbase | offs[j]) & cm) == cv;
-            v[j].x = p ? y.x : x.x;
-            v[j].y = p ? y.y : x.y;
-            v[j1].x = p ? x.x : y.x;
-            v[j1].y = p ? x.y : y.y;
-        }
-    }
-
-    template <int S = 0>
-    static __device__ __forceinline__ void dispatch_u(int slot, C (&v)[NR], const Mat<R> &m, uint32_t cm, uint32_t cv,
-                                                      uint32_t tbase, const uint32_t (&offs)[NR])
-    {
-        if constexpr (S < LOG_R) {
-            if (slot == S) {
-                if (cm == 0)
-                    bfly<S, false>(v, m, cm, cv, tbase, offs);
-                else
-                    bfly<S, true>(v, m, cm, cv, tbase, offs);
-            } else {
-                dispatch_u<S + 1>(slot, v, m, cm, cv, tbase, offs);
-            }
-        }
-    }
-
-    template <int S = 0>
-    static __device__ __forceinline__ void dispatch_x(int slot, C (&v)[NR], uint32_t cm, uint32_t cv, uint32_t tbase,
-                                                      const uint32_t (&offs)[NR])
-    {
-        if constexpr (S < LOG_R) {
-            if (slot == S)
-                xswap<S>(v, cm, cv, tbase, offs);
+            if (SW)
+                m.apply(v[j1], v[j]);
             else
-                dispatch_x<S + 1>(slot, v, cm, cv, tbase, offs);
+                m.apply(v[j], v[j1]);
         }
     }
 
-    template <typename P> static __device__ __forceinline__ uint32_t bitperm(uint32_t x, P perm)
+    // Controlled 2x2.  A pair takes part when its register pattern has every
+    // control slot set, (j & rm) == rv with rv = rm & ~fl (a scalar test), and,
+    // with LANE, the lane has every control thread bit set (lp, a select).
+    template <int S, bool SW, bool LANE>
+    static __device__ __forceinline__ void bfly_c(C (&v)[NR], const Mat<R> &m, uint32_t rm, uint32_t rv, bool lp)
     {
-        uint32_t y = 0;
 #pragma unroll
-        for (int b = 0; b < K; ++b)
-            y |= ((x >> b) & 1u) << perm[b];
-        return y;
+        for (int jj = 0; jj < NR / 2; ++jj) {
+            const int j = pair_lo<S>(jj), j0 = SW ? (j | (1 << S)) : j, j1 = SW ? j : (j | (1 << S));
+            if (((uint32_t)j & rm) == rv) {
+                if (LANE) {
+                    C x = v[j0], y = v[j1];
+                    m.apply(x, y);
+                    v[j0].x = lp ? x.x : v[j0].x;
+                    v[j0].y = lp ? x.y : v[j0].y;
+                    v[j1].x = lp ? y.x : v[j1].x;
+                    v[j1].y = lp ? y.y : v[j1].y;
+                } else {
+                    m.apply(v[j0], v[j1]);
+                }
+            }
+        }
     }
 
-    // deposit of the tile's register-slot bits j into the positions pos[LOG_NT..K)
-    template <typename A> static __device__ __forceinline__ uint64_t slot_offset(const A &a, int j)
+    // exchange on slot S with any controls: scalar test per pair, lane select
+    template <int S>
+    static __device__ __forceinline__ void xswap_c(C (&v)[NR], uint32_t rm, uint32_t rv, bool lp)
     {
-        uint64_t dj = 0;
 #pragma unroll
-        for (int b = 0; b < LOG_R; ++b)
-            if ((j >> b) & 1)
-                dj |= 1ull << a.pos[LOG_NT + b];
-        return dj;
+        for (int jj = 0; jj < NR / 2; ++jj) {
+            const int j = pair_lo<S>(jj), j1 = j | (1 << S);
+            if (((uint32_t)j & rm) == rv) {
+                const C x = v[j], y = v[j1];
+                v[j].x = lp ? y.x : x.x;
+                v[j].y = lp ? y.y : x.y;
+                v[j1].x = lp ? x.x : y.x;
+                v[j1].y = lp ? x.y : y.y;
+            }
+        }
+    }
+
+    template <int S, bool SW>
+    static __device__ __forceinline__ void apply_u(C (&v)[NR], const Mat<R> &m, uint32_t rm, uint32_t lm, uint32_t rv,
+                                                   bool lp)
+    {
+        if ((rm | lm) == 0)
+            bfly<S, SW>(v, m);
+        else if (lm == 0)
+            bfly_c<S, SW, false>(v, m, rm, rv, lp);
+        else
+            bfly_c<S, SW, true>(v, m, rm, rv, lp);
+    }
+
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_u(int slot, uint32_t sw, C (&v)[NR], const Mat<R> &m, uint32_t rm,
+                                                      uint32_t lm, uint32_t rv, bool lp)
+    {
+        if (slot == S || S == LOG_R - 1) {
+            if (sw)
+                apply_u<S, true>(v, m, rm, lm, rv, lp);
+            else
+                apply_u<S, false>(v, m, rm, lm, rv, lp);
+        } else if constexpr (S + 1 < LOG_R) {
+            dispatch_u<S + 1>(slot, sw, v, m, rm, lm, rv, lp);
+        }
+    }
+
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_x(int slot, C (&v)[NR], uint32_t rm, uint32_t lm, uint32_t rv,
+                                                      bool lp)
+    {
+        if (slot == S || S == LOG_R - 1) {
+            if (lm == 0) {
+                // register controls only: the exchange as a 2x2 with the X
+                // matrix on the selected pairs (exact: products with 0 and 1)
+                Mat<R> x;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    x.a[q] = (q == 2 || q == 4) ? (R)1 : (R)0;
+                bfly_c<S, false, false>(v, x, rm, rv, lp);
+            } else {
+                xswap_c<S>(v, rm, rv, lp);
+            }
+        } else if constexpr (S + 1 < LOG_R) {
+            dispatch_x<S + 1>(slot, v, rm, lm, rv, lp);
+        }
+    }
+
+    // flip the sign bit where sg has it set (sg is 0 or the sign mask)
+    static __device__ __forceinline__ R flip_sign(R x, uint32_t sg)
+    {
+        if constexpr (sizeof(R) == 8)
+            return __builtin_bit_cast(R, __builtin_bit_cast(uint64_t, x) ^ ((uint64_t)sg << 32));
+        else
+            return __builtin_bit_cast(R, __builtin_bit_cast(uint32_t, x) ^ sg);
+    }
+
+    // register tile bit of slot bit s under the packed register bits regs
+    static __device__ __forceinline__ uint32_t rbit(uint32_t regs, int s) { return (regs >> (4 * s)) & 15u; }
+
+    // Visit the slots j in Gray-code order with the XOR over the set bits s of
+    // j of basis(s): consecutive slots differ in one bit, so each value costs
+    // one XOR and only one is live at a time.
+    template <typename T, typename B, typename Fn>
+    static __device__ __forceinline__ void for_slots(B basis, Fn fn)
+    {
+        T acc = 0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i)
+                acc ^= basis(__builtin_ctz(i));
+            fn(i ^ (i >> 1), acc);
+        }
+    }
+
+    // the thread id deposited into tile bits: thread bit i goes to tile bit
+    // (map >> 4i) & 15 (the lane map of an OP_REMAP)
+    static __device__ __forceinline__ uint32_t lane_bits(uint64_t map, uint32_t tid)
+    {
+        uint32_t tb = 0;
+#pragma unroll
+        for (int i = 0; i < LOG_NT; ++i)
+            tb |= ((tid >> i) & 1u) << ((map >> (4 * i)) & 15u);
+        return tb;
+    }
+
+    // the thread id deposited into physical positions: thread bit i goes to lane[i]
+    template <typename P> static __device__ __forceinline__ uint64_t lane_offset(P lane, uint32_t tid)
+    {
+        uint64_t d = 0;
+#pragma unroll
+        for (int i = 0; i < LOG_NT; ++i)
+            d |= (uint64_t)((tid >> i) & 1u) << lane[i];
+        return d;
+    }
+
+    // the tile number with a zero inserted at every tile position (ascending)
+    template <typename A> static __device__ __forceinline__ uint64_t tile_base(const A &a, uint64_t tile)
+    {
+        uint64_t base = tile;
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const int p = a.pos[b];
+            base = ((base >> p) << (p + 1)) | (base & ((1ull << p) - 1));
+        }
+        return base;
+    }
+
+    // registers <-> LDS at the tile-local indices of the layout (tbase, regs, fl)
+    static __device__ __forceinline__ void to_lds(unsigned char *lds, const C (&v)[NR], uint32_t tbase, uint32_t regs,
+                                                   uint32_t fl)
+    {
+        const uint32_t tb = tbase * CB;
+        for_slots<uint32_t>([&](int s) { return CB << rbit(regs, s); }, [&](int j, uint32_t o) {
+            uint32_t fo = 0;  // the flipped slot bits of the pattern
+#pragma unroll
+            for (int s = 0; s < LOG_R; ++s)
+                fo ^= ((fl >> s) & 1u) ? (CB << rbit(regs, s)) : 0u;
+            *reinterpret_cast<C *>(lds + (tb | (o ^ fo))) = v[j];
+        });
+    }
+    static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs)
+    {
+        const uint32_t tb = tbase * CB;
+        for_slots<uint32_t>([&](int s) { return CB << rbit(regs, s); },
+                            [&](int j, uint32_t o) { v[j] = *reinterpret_cast<const C *>(lds + (tb | o)); });
     }
 
     using OpPtr = const __attribute__((address_space(4))) TileOp *;
 
-    // the fields of one operation, held in scalar registers
+    // the fields of one operation, read together (scalar registers)
     struct OpV {
         int32_t kind, slot;
-        uint32_t cmask, regs;
+        uint32_t rmask, lmask, tlane;
         uint64_t hmask, hbit;
         double m[8];
     };
-
     static __device__ __forceinline__ OpV fetch(OpPtr ops, int i)
     {
         OpV o;
         o.kind = ops[i].kind;
         o.slot = ops[i].slot;
-        o.cmask = ops[i].cmask;
-        o.regs = ops[i].regs;
+        o.rmask = ops[i].rmask;
+        o.lmask = ops[i].lmask;
+        o.tlane = ops[i].tlane;
         o.hmask = ops[i].hmask;
         o.hbit = ops[i].hbit;
 #pragma unroll
@@ -147,216 +270,236 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return o;
     }
 
-    // Register slot j holds the amplitude of register pattern j ^ fl: an
-    // exchange (X) whose control is the same for the whole tile flips a bit of
-    // fl instead of moving data.  F is fl deposited into tile bits, so the
-    // tile-local index of slot j is (tbase | offs[j]) ^ F.
     // Per-tile read-out of the final amplitudes: sum |a|^2 and sum |a|^2 (1 - 2 b)
     // where b is the bit at physical position zpos (the first qubit), reduced
     // over the workgroup in a fixed order and written to out[0..1].
     struct Readout {
-        double *out;  // NULL: none
+        double *out;  // NULL: none; else two doubles per tile, tile t at out + 2 (t - t_first) / t_step
         int zpos;
     };
 
-    // One tile.  A is TileArgs, read from kernel arguments or from device
-    // memory; tile is the tile number (index over the positions outside it).
-    template <typename A>
-    static __device__ __forceinline__ void run(const A &a, unsigned char *lds_raw, uint64_t tile, Readout ro)
+    // Tiles t_first, t_first + t_step, ... below t_end.  A is TileArgs, read
+    // from kernel arguments or from device memory.
+    template <bool OPF, typename A>
+    static __device__ __forceinline__ void run_range(const A &a, unsigned char *lds, uint64_t t_first, uint64_t t_end,
+                                                     uint64_t t_step, Readout ro)
     {
-        C *lds = reinterpret_cast<C *>(lds_raw);
         C *st = reinterpret_cast<C *>(a.state);
         OpPtr ops = (OpPtr)(a.ops);
         const uint32_t tid = threadIdx.x;
-
-        // base index: the tile number with a zero inserted at every tile position
-        // (positions ascending)
-        uint64_t base = tile;
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-            const int p = a.pos[b];
-            base = ((base >> p) << (p + 1)) | (base & ((1ull << p) - 1));
-        }
-        uint64_t dtid = 0;
-#pragma unroll
-        for (int b = 0; b < LOG_NT; ++b)
-            dtid |= (uint64_t)((tid >> b) & 1u) << a.pos[b];
-
-        C v[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-            v[j] = st[base + dtid + slot_offset(a, j)];
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-            lds[j * NT + tid] = v[j];
-        __syncthreads();
-
-        uint32_t offs[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-            offs[j] = 0;
-        uint32_t tbase = 0, regs = 0, fl = 0, F = 0;
-        bool have = false;
-
         const int n_ops = a.n_ops;
-        for (int oi = 0; oi < n_ops; ++oi) {
-            const OpV cur = fetch(ops, oi);
-            const int kind = cur.kind;
-            if (kind == OP_REMAP) {
-                if (have) {
-#pragma unroll
-                    for (int j = 0; j < NR; ++j)
-                        lds[(tbase | offs[j]) ^ F] = v[j];
-                    __syncthreads();
-                }
-                regs = cur.regs;
-                uint32_t regmask = 0;
-                uint32_t rb[LOG_R];
-#pragma unroll
-                for (int s = 0; s < LOG_R; ++s) {
-                    rb[s] = (regs >> (4 * s)) & 15u;
-                    regmask |= 1u << rb[s];
-                }
-#pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    uint32_t o = 0;
-#pragma unroll
-                    for (int s = 0; s < LOG_R; ++s)
-                        if ((j >> s) & 1)
-                            o |= 1u << rb[s];
-                    offs[j] = o;
-                }
-                tbase = 0;
-                int tbit = 0;
-#pragma unroll
-                for (int b = 0; b < K; ++b) {
-                    if (!((regmask >> b) & 1u)) {
-                        tbase |= ((tid >> tbit) & 1u) << b;
-                        ++tbit;
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    v[j] = lds[tbase | offs[j]];
-                __syncthreads();
-                fl = 0;
-                F = 0;
-                have = true;
-            } else if ((base & cur.hmask) == cur.hmask) {
-                const uint32_t cm = cur.cmask;
-                const uint32_t cv = cm & ~F;  // (idx ^ F) & cm == cm  <=>  idx & cm == cm & ~F
-                if (kind == OP_U) {
-                    Mat<R> m;
-                    const bool sw = (fl >> cur.slot) & 1u;
-                    // with the slot's pattern bit flipped, rows and columns trade places
-                    m.a[0] = (R)(sw ? cur.m[6] : cur.m[0]);
-                    m.a[1] = (R)(sw ? cur.m[7] : cur.m[1]);
-                    m.a[2] = (R)(sw ? cur.m[4] : cur.m[2]);
-                    m.a[3] = (R)(sw ? cur.m[5] : cur.m[3]);
-                    m.a[4] = (R)(sw ? cur.m[2] : cur.m[4]);
-                    m.a[5] = (R)(sw ? cur.m[3] : cur.m[5]);
-                    m.a[6] = (R)(sw ? cur.m[0] : cur.m[6]);
-                    m.a[7] = (R)(sw ? cur.m[1] : cur.m[7]);
-                    dispatch_u(cur.slot, v, m, cm, cv, tbase, offs);
-                } else if (kind == OP_X) {
-                    if (cm == 0) {
-                        fl ^= 1u << cur.slot;
-                        F ^= 1u << ((regs >> (4 * cur.slot)) & 15u);
-                    } else {
-                        dispatch_x(cur.slot, v, cm, cv, tbase, offs);
-                    }
-                } else if (kind == OP_NEG) {
-#pragma unroll
-                    for (int j = 0; j < NR; ++j) {
-                        const bool p = ((tbase | offs[j]) & cm) == cv;
-                        v[j].x = p ? -v[j].x : v[j].x;
-                        v[j].y = p ? -v[j].y : v[j].y;
-                    }
-                } else {  // OP_DIAG
-                    const R d0r = (R)cur.m[0], d0i = (R)cur.m[1], d1r = (R)cur.m[2], d1i = (R)cur.m[3];
-                    const int tb = cur.slot;
-                    const bool hsel = (base & cur.hbit) != 0;
-#pragma unroll
-                    for (int j = 0; j < NR; ++j) {
-                        const uint32_t idx = (tbase | offs[j]) ^ F;
-                        const bool p = (idx & cm) == cm;
-                        const bool sel = tb >= 0 ? ((idx >> tb) & 1u) != 0 : hsel;
-                        const R dr = sel ? d1r : d0r, di = sel ? d1i : d0i;
-                        const C x = v[j];
-                        const R nr = dr * x.x - di * x.y, ni = dr * x.y + di * x.x;
-                        v[j].x = p ? nr : x.x;
-                        v[j].y = p ? ni : x.y;
-                    }
-                }
-            }
-        }
+        const bool dload = (a.io & 1u) != 0, dstore = (a.io & 2u) != 0;
 
-        if (have) {
-            if (a.has_perm) {
-#pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    lds[bitperm((tbase | offs[j]) ^ F, a.perm)] = v[j];
+        // Load and store layouts: a thread's offset plus, per slot, the XOR
+        // over its set bits of the slot bits' position bits.
+        const uint64_t lane_ld = lane_offset(a.ld_lane, tid);
+        const uint64_t lane_st = lane_offset(a.st_lane, tid);
+        auto pbit_ld = [&](int s) { return 1ull << a.ld_reg[s]; };
+        auto pbit_st = [&](int s) { return 1ull << a.st_reg[s]; };
+
+        // v holds the tile being processed; the next tile of the workgroup is
+        // loaded into w while v is processed and moves into v after v's
+        // stores are issued, so the wait for it never waits for those stores
+        C v[NR];
+        auto load = [&](C(&dst)[NR], uint64_t tile) {
+            const C *src = st + tile_base(a, tile) + lane_ld;
+            for_slots<uint64_t>(pbit_ld, [&](int j, uint64_t o) { dst[j] = src[o]; });
+        };
+        if (t_first < t_end)
+            load(v, t_first);
+        // wait for the first tile here, so that the loop's own waits are only
+        // those for the prefetched tile (vmcnt(0): expcnt and lgkmcnt left at
+        // their maxima)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+
+        for (uint64_t t = t_first; t < t_end; t += t_step) {
+            C w[NR];
+            const bool more = t + t_step < t_end;
+            if (more)
+                load(w, t + t_step);
+            const uint64_t base = tile_base(a, t);
+
+            uint32_t regs = 0, tbase = 0, fl = 0, F = 0;
+            bool have = false;
+            int oi = 0;
+            if (dload) {
+                regs = ops[0].rmask;
+                tbase = lane_bits(ops[0].hbit, tid);
+                have = true;
+                oi = 1;
             } else {
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    lds[(tbase | offs[j]) ^ F] = v[j];
+                    *reinterpret_cast<C *>(lds + (tid + j * NT) * CB) = v[j];
+                lds_sync();
             }
-            __syncthreads();
+
+            // The fields of the next operation are loaded while the current one
+            // runs, so the scalar-load latency hides behind its arithmetic.
+            // With OPF the fields of the next operation are loaded while the
+            // current one runs.
+            OpV cur;
+            if constexpr (OPF)
+                cur = fetch(ops, oi < n_ops ? oi : 0);
+            for (; oi < n_ops; ++oi) {
+                OpV nx;
+                if constexpr (OPF) {
+                    nx = fetch(ops, oi + 1 < n_ops ? oi + 1 : oi);
+                } else {
+                    cur = fetch(ops, oi);
+                    // issue all of the operation's scalar loads together, so
+                    // that one wait covers them
+                    __asm__ __volatile__("" ::"s"(cur.kind), "s"(cur.hmask), "s"(cur.m[0]), "s"(cur.m[7]));
+                }
+                const int kind = cur.kind;
+                if (kind == OP_REMAP) {
+                    if (have) {
+                        to_lds(lds, v, tbase, regs, fl);
+                        lds_sync();
+                    }
+                    regs = cur.rmask;
+                    tbase = lane_bits(cur.hbit, tid);
+                    from_lds(lds, v, tbase, regs);
+                    lds_sync();
+                    fl = 0;
+                    F = 0;
+                    have = true;
+                } else if ((base & cur.hmask) == cur.hmask) {
+                    const uint32_t rm = cur.rmask, lm = cur.lmask;
+                    const uint32_t rv = rm & ~fl;
+                    const bool lp = (tbase & lm) == lm;
+                    const int slot = cur.slot;
+                    if (kind == OP_U) {
+                        Mat<R> m;
 #pragma unroll
-            for (int j = 0; j < NR; ++j)
-                v[j] = lds[j * NT + tid];
-        } else {
+                        for (int q = 0; q < 8; ++q)
+                            m.a[q] = (R)cur.m[q];
+                        dispatch_u(slot, (fl >> slot) & 1u, v, m, rm, lm, rv, lp);
+                    } else if (kind == OP_X) {
+                        if ((rm | lm) == 0) {
+                            fl ^= 1u << slot;
+                            F ^= 1u << rbit(regs, slot);
+                        } else {
+                            dispatch_x(slot, v, rm, lm, rv, lp);
+                        }
+                    } else if (kind == OP_NEG) {
+                        // sign flips: the slot test is scalar, the lane test a mask
+                        const uint32_t sg = lp ? 0x80000000u : 0u;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const uint32_t t = (uint32_t)(j * NT) + tid;
-                const uint32_t src = a.has_perm ? bitperm(t, a.pinv) : t;
-                v[j] = lds[src];
+                        for (int j = 0; j < NR; ++j) {
+                            const uint32_t sj = ((uint32_t)j & rm) == rv ? sg : 0u;
+                            v[j].x = flip_sign(v[j].x, sj);
+                            v[j].y = flip_sign(v[j].y, sj);
+                        }
+                    } else {  // OP_DIAG: target on register slot `slot`, thread bit tlane, or outside (hbit)
+                        R d0r = (R)cur.m[0], d0i = (R)cur.m[1], d1r = (R)cur.m[2], d1i = (R)cur.m[3];
+                        // lanes outside the thread-bit controls multiply by 1
+                        d0r = lp ? d0r : (R)1;
+                        d0i = lp ? d0i : (R)0;
+                        d1r = lp ? d1r : (R)1;
+                        d1i = lp ? d1i : (R)0;
+                        const bool lsel = cur.tlane ? (tbase & cur.tlane) != 0 : (base & cur.hbit) != 0;
+                        const R lr = lsel ? d1r : d0r, li = lsel ? d1i : d0i;
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) {
+                            if (((uint32_t)j & rm) == rv) {
+                                R dr = lr, di = li;
+                                if (slot >= 0) {
+                                    const bool sl = ((((uint32_t)j ^ fl) >> slot) & 1u) != 0;
+                                    dr = sl ? d1r : d0r;
+                                    di = sl ? d1i : d0i;
+                                }
+                                const C x = v[j];
+                                v[j].x = fmadd(dr, x.x, -di * x.y);
+                                v[j].y = fmadd(dr, x.y, di * x.x);
+                            }
+                        }
+                    }
+                }
+                if constexpr (OPF)
+                    cur = nx;
+            }
+
+            // Store.  Direct: slot j holds pattern j ^ fl of the last layout,
+            // whose offset is the slot's offset XOR the flipped bits' offset.
+            const bool direct = have && dstore;
+            if (have && !dstore) {
+                to_lds(lds, v, tbase, regs, fl);
+                lds_sync();
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    v[j] = *reinterpret_cast<const C *>(lds + (tid + j * NT) * CB);
+            }
+            uint64_t dfl = 0;
+            if (direct) {
+#pragma unroll
+                for (int s = 0; s < LOG_R; ++s)
+                    dfl ^= ((fl >> s) & 1u) ? pbit_st(s) : 0ull;
+            }
+            C *dst = st + base + lane_st;
+            double nrm = 0.0, z = 0.0;
+            for_slots<uint64_t>(pbit_st, [&](int j, uint64_t o) {
+                dst[o ^ dfl] = v[j];
+                if (ro.out) {
+                    const uint64_t phys = base + lane_st + (o ^ dfl);
+                    const double re = (double)v[j].x, im = (double)v[j].y, p = re * re + im * im;
+                    nrm += p;
+                    z += ((phys >> ro.zpos) & 1ull) ? -p : p;
+                }
+            });
+            if (ro.out)
+                reduce_pair(nrm, z, ro.out + 2 * ((t - t_first) / t_step), reinterpret_cast<double *>(lds));
+            lds_sync();  // the next tile reuses the LDS buffer
+            if (more) {
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    v[j] = w[j];
             }
         }
-#pragma unroll
-        for (int j = 0; j < NR; ++j)
-            st[base + dtid + slot_offset(a, j)] = v[j];
-        if (ro.out)
-            readout(a, v, base, dtid, ro, reinterpret_cast<double *>(lds_raw));
     }
 
-    template <typename A>
-    static __device__ __forceinline__ void readout(const A &a, const C (&v)[NR], uint64_t base, uint64_t dtid,
-                                                   Readout ro, double *red)
+    // Sum nrm and z over the workgroup in a fixed order; thread 0 writes out[0..1].
+    static __device__ __forceinline__ void reduce_pair(double nrm, double z, double *out, double *red)
     {
         const uint32_t tid = threadIdx.x;
-        double nrm = 0.0, z = 0.0;
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const uint64_t phys = base + dtid + slot_offset(a, j);
-            const double re = (double)v[j].x, im = (double)v[j].y, p = re * re + im * im;
-            nrm += p;
-            z += ((phys >> ro.zpos) & 1ull) ? -p : p;
-        }
-        __syncthreads();  // the tile buffer is reused for the reduction
+        lds_sync();
         red[tid] = nrm;
         red[NT + tid] = z;
-        __syncthreads();
+        lds_sync();
 #pragma unroll
         for (int w = NT / 2; w > 0; w >>= 1) {
             if ((int)tid < w) {
                 red[tid] += red[tid + w];
                 red[NT + tid] += red[NT + tid + w];
             }
-            __syncthreads();
+            lds_sync();
         }
         if (tid == 0) {
-            ro.out[0] = red[0];
-            ro.out[1] = red[NT];
+            out[0] = red[0];
+            out[1] = red[NT];
         }
+        lds_sync();
     }
 };
 
+// One workgroup per group of tiles: workgroup b takes tiles b, b + G, ...
+#ifndef QSIM_TILE_PERSIST
+#define QSIM_TILE_PERSIST 0
+#endif
+#ifndef QSIM_TILE_OPF
+#define QSIM_TILE_OPF 0
+#endif
+
 template <typename R, int LOG_NT, int LOG_R>
-__global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
+__global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a, uint64_t n_tiles)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    TileKernel<R, LOG_NT, LOG_R>::run(a, lds_raw, blockIdx.x, {nullptr, 0});
+    if (QSIM_TILE_PERSIST)
+        TileKernel<R, LOG_NT, LOG_R>::template run_range<QSIM_TILE_OPF>(a, lds_raw, blockIdx.x, n_tiles, gridDim.x,
+                                                                        {nullptr, 0});
+    else
+        TileKernel<R, LOG_NT, LOG_R>::template run_range<QSIM_TILE_OPF>(a, lds_raw, blockIdx.x, blockIdx.x + 1, 1,
+                                                                        {nullptr, 0});
 }
 
 template <typename R, int LOG_NT, int LOG_R>
@@ -364,18 +507,27 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
 {
     using C = typename Cx<R>::T;
     constexpr size_t bytes = sizeof(C) << (LOG_NT + LOG_R);
-    // launches above the default dynamic LDS limit need the attribute first
-    static bool attr_set = bytes <= 65536;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess)
-            fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
-        attr_set = true;
+    const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>);
+    // launches above the default dynamic LDS limit need the attribute first;
+    // the grid is the number of workgroups the device holds at once
+    static int grid_cap = 0;
+    if (grid_cap == 0) {
+        if (bytes > 65536) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess)
+                fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
+        }
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1 << LOG_NT, bytes) != hipSuccess)
+            fail(QS_ERR_HIP, "tile kernel occupancy query failed");
+        grid_cap = std::max(1, cus) * std::max(1, per_cu);
     }
-    if (n_tiles > 0x7fffffffull)
-        fail(QS_ERR_UNSUPPORTED, "too many tiles for one launch");
-    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)n_tiles), dim3(1 << LOG_NT), bytes, st, a);
+    const uint64_t grid = QSIM_TILE_PERSIST ? std::min<uint64_t>(n_tiles, (uint64_t)grid_cap) : n_tiles;
+    if (grid == 0)
+        return;
+    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)grid), dim3(1 << LOG_NT), bytes, st, a, n_tiles);
     check_launch("tile pass");
 }
 

@@ -22,7 +22,7 @@ except ImportError:  # pragma: no cover - torch is part of the image
     torch = None
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("QSIM_LIB", os.path.join(_HERE, "libqsim.so"))
+LIB_PATH = os.environ.get("QSIM_LIB") or os.path.join(_HERE, "libqsim.so")
 
 QS_C64, QS_C128 = 0, 1
 QS_FORM_PLAIN, QS_FORM_PASS = 0, 1
