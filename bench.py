@@ -202,7 +202,7 @@ def serve(a):
 
     trace = request_trace(count=a.requests, rate=a.rate)
     reqs = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in trace]
-    srv = Server("c64", k_tile=10, max_swaps=16, pinned=3, reg_bits=3, hbm_budget=200e9, max_slots=256)
+    srv = Server("c64", k_tile=10, max_swaps=16, pinned=3, hbm_budget=200e9, max_slots=256)
     # warm-up: one small request outside the measured trace
     srv.serve([dict(id=-1, arrival=0.0, n=12, gates=layered_circuit(12, 4, 1), samples=[0])], realtime=False)
     res, rec = srv.serve(reqs, realtime=True, log=lambda m: print("serve " + m, file=sys.stderr, flush=True))
