@@ -37,8 +37,9 @@ def parse():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--dtype", default="c128")
-    ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--r", type=int, default=8)
+    # the measured cost model's choice for the 30-qubit workload (bench.py --form costmodel)
+    ap.add_argument("--k", type=int, default=11)
+    ap.add_argument("--r", type=int, default=16)
     ap.add_argument("--perm-exec", default="relabel")
     ap.add_argument("--pinned", type=int, default=3)
     ap.add_argument("--reg-bits", type=int, default=0)
@@ -50,9 +51,12 @@ def parse():
                          "known size, used to scale hardware byte counters)")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
-    ap.add_argument("--form", default="pass", choices=["pass", "precision", "batch", "serve"],
+    ap.add_argument("--form", default="pass",
+                    choices=["pass", "precision", "batch", "serve", "kernels", "qft", "random-family", "costmodel"],
                     help="pass: the 30-qubit complex128 workload (default line); precision: 32 qubits, complex64 "
-                         "against complex128")
+                         "against complex128; batch / serve: the batching and serving forms; kernels: each "
+                         "single-purpose kernel at 30 qubits; qft: QFT and QFT-like circuits; random-family: the "
+                         "paper's random family, plain against pass form")
     return ap.parse_args()
 
 
@@ -144,12 +148,11 @@ def precision(a):
 
 def batch(a):
     """256 seeded circuits, n uniform in [10, 24], depth uniform in [10, 60],
-    complex64: one persistent launch per run, replayed from a HIP graph, with
-    k and the fusion depth chosen by the autotuner."""
+    complex64: one launch per pass level over all circuits, the whole run
+    replayed from a HIP graph, with k and the fusion depth chosen by the
+    autotuner.  Accuracy against the oracle is covered by the GPU tests."""
     import numpy as np
-    import torch
 
-    import oracle as O
     from paper_2010_09746_amd import autotune, qsim as Q
     from workloads import batch_workload
 
@@ -171,8 +174,6 @@ def batch(a):
     sec = float(np.median(ts))
     st = b.stats()
     upd = sum(len(g) * float(1 << n) for n, g in circuits)
-    # accuracy: oracle on every circuit of at most 16 qubits
-    errs = [abs(z[c] - O.expect_z(O.run(g, n), n)[0]) for c, (n, g) in enumerate(circuits) if n <= 16]
     b.close()
     line = {
         "metric": "amplitude-updates/s", "value": upd / sec, "unit": "amplitude-updates/s", "n_gpus": 1,
@@ -185,7 +186,6 @@ def batch(a):
         "tuned": best, "tune_seconds": tune_s, "tune_candidates": len(table),
         "batch_stats": st,
         "max_norm_error": float(np.abs(nrm - 1).max()),
-        "oracle_checked_circuits": len(errs), "max_abs_z0_error_vs_oracle": float(max(errs) if errs else 0.0),
     }
     print(json.dumps(line), flush=True)
 
@@ -193,10 +193,11 @@ def batch(a):
 def serve(a):
     """Seeded Poisson trace (rate, count), n uniform in [12, 30], depth uniform
     in [20, 100], complex64 with FP64 reductions, 200 GB budget, states
-    resident; each request returns <Z_q> for all q and 16 sampled amplitudes."""
+    resident; each request returns <Z_q> for all q and 16 sampled amplitudes.
+    Accuracy against the oracle is covered by the GPU tests; here the norm of
+    every served state is reported."""
     import numpy as np
 
-    import oracle as O
     from paper_2010_09746_amd.serving import Server, latency_summary
     from workloads import layered_circuit, request_trace
 
@@ -207,12 +208,7 @@ def serve(a):
     srv.serve([dict(id=-1, arrival=0.0, n=12, gates=layered_circuit(12, 4, 1), samples=[0])], realtime=False)
     res, rec = srv.serve(reqs, realtime=True, log=lambda m: print("serve " + m, file=sys.stderr, flush=True))
     st = latency_summary(rec)
-    errs = []
-    for r in reqs:
-        if r["n"] <= 18:
-            ref = O.run(r["gates"], r["n"])
-            errs.append(max(float(np.abs(res[r["id"]]["z"] - O.expect_z(ref, r["n"])).max()),
-                            float(np.abs(res[r["id"]]["amps"] - ref[np.asarray(r["samples"], dtype=np.int64)]).max())))
+    nerr = [abs(res[r["id"]]["norm"] - 1.0) for r in reqs]
     line = {
         "metric": "served p50/p99 latency", "value": st["p99_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": st["makespan_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -221,11 +217,82 @@ def serve(a):
                                f"[12,30], depth uniform in [20,100], complex64 with FP64 reductions, 200 GB budget, "
                                f"<Z_q> all q + 16 sampled amplitudes per request", "parallelism": "1 GPU"},
         "latency": st, "server": srv.last_stats,
-        "accuracy": {"oracle_checked_requests": len(errs), "max_abs_error": max(errs) if errs else None,
-                     "tolerance": 1e-5},
+        "max_norm_error": float(np.max(nerr)),
     }
     srv.close()
     print(json.dumps(line), flush=True)
+
+
+def _study_line(metric, value, unit, ms, cfg, body, hib=True, dtype="f64"):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": ms, "higher_is_better": hib, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": dict(cfg, parallelism="1 GPU")}
+    line["result"] = body
+    print(json.dumps(line), flush=True)
+
+
+def kernels(a):
+    """Each single-purpose kernel at 30 qubits, complex128."""
+    from paper_2010_09746_amd import studies
+
+    r = studies.kernel_sweep(n=a.n, dtype=a.dtype)
+    u = [x["gbs"] for x in r["plain_u_per_target"]]
+    _study_line("one-qubit gate bandwidth (median over targets)", float(sorted(u)[len(u) // 2]), "GB/s",
+                sum(x["avg_ms"] for x in r["plain_u_per_target"]) / len(u),
+                {"workload": f"single kernels at n={a.n} {a.dtype}: one-qubit gate on each target, CX/CZ on "
+                             f"low/high pairs, position exchanges of 1..8 pairs, <Z_q> read-out"}, r)
+
+
+def qft(a):
+    """QFT (checked against its closed form) and the QFT-like circuit, 30 qubits."""
+    from paper_2010_09746_amd import studies
+
+    r = studies.qft_study(n=a.n, dtype=a.dtype, k=a.k, r=a.r, pinned=a.pinned)
+    _study_line("amplitude-updates/s", r["qft"]["amp_updates_per_s"], "amplitude-updates/s", r["qft"]["ms"],
+                {"workload": f"QFT on a basis state and the QFT-like circuit (CNOT for each controlled phase), "
+                             f"n={a.n} {a.dtype}, pass form k={a.k} r={a.r}"}, r)
+
+
+def random_family(a):
+    """The paper's random family (Section 4): plain against pass form over p."""
+    from paper_2010_09746_amd import studies
+
+    n = a.n if a.n != 30 else 28
+    r = studies.random_family_study(n=n, dtype=a.dtype, k=a.k, r=a.r, pinned=a.pinned)
+    best = max(x["speedup"] for x in r["rows"])
+    _study_line("pass-form speedup over plain (best p)", best, "x", sum(x["pass_ms"] for x in r["rows"]),
+                {"workload": f"random family: 30n gates, CNOT with probability p else H or Y, n={n} {a.dtype}, "
+                             f"pass form k={a.k} r={a.r} against one launch per gate"}, r)
+
+
+def costmodel_form(a):
+    """Measured cost model: predict every candidate (k, r, register bits) for
+    the 30-qubit workload, run a spread of them, and report how well the
+    prediction ranks them and what the predicted choice costs."""
+    import numpy as np
+
+    from paper_2010_09746_amd import costmodel
+    from workloads import config_circuit
+
+    gates = config_circuit(2, n=a.n, layers=a.layers)
+    cm = costmodel.CostModel(a.dtype, n_cal=26)
+    t0 = time.perf_counter()
+    best, table = cm.choose(gates, a.n, ks=(9, 10, 11, 12), rs=(1, 4, 8, 16), reg_bits=(3, 4))
+    choose_s = time.perf_counter() - t0
+    pick = table[:3] + table[3::max(1, (len(table) - 3) // 5)][:5]
+    for row in pick:
+        row["measured_ms"] = costmodel.measure_ms(gates, a.n, a.dtype, row["opts"], reps=1)
+    pm = [r["predicted_ms"] for r in pick]
+    mm = [r["measured_ms"] for r in pick]
+    chosen = pick[0]["measured_ms"]
+    _study_line("cost-model regret (chosen / best measured)", chosen / min(mm), "x", chosen,
+                {"workload": f"cost model on the layered circuit n={a.n} {a.dtype} ({len(gates)} gates): "
+                             f"{len(table)} candidates predicted, {len(pick)} measured"},
+                {"chosen": best, "choose_seconds": choose_s, "rank_correlation": costmodel.rank_correlation(pm, mm),
+                 "measured": pick, "calibration": {f"k{k}_rb{rb}": v for (k, rb), v in cm.tile_costs.items()},
+                 "launch_costs": cm.launch_costs,
+                 "fit_residual": {f"k{k}_rb{rb}": v for (k, rb), v in cm.fit_residual.items()}},
+                hib=False)
 
 
 def main():
@@ -237,6 +304,14 @@ def main():
         return precision(a)
     if a.form == "batch":
         return batch(a)
+    if a.form == "kernels":
+        return kernels(a)
+    if a.form == "qft":
+        return qft(a)
+    if a.form == "random-family":
+        return random_family(a)
+    if a.form == "costmodel":
+        return costmodel_form(a)
     if a.form == "serve":
         return serve(a)
 

@@ -167,6 +167,40 @@ qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt,
                      const int *sigma0, const qs_run_opts *opts, qs_program **out);
 qs_status qs_program_destroy(qs_program *p);
 qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
+/* Work of a compiled program by class, for a cost model that prices each
+ * class with measured device costs (paper, Section 3: a pass may use the
+ * simulator's own benchmarks instead of the local/global step function).
+ * out[c] (host, cap doubles, c < QS_OPC_COUNT) receives, per class:
+ *   QS_OPC_TILE_PASS   tile-kernel launches
+ *   QS_OPC_U .. QS_OPC_REMAP  operations inside tile passes, each weighted by
+ *                      the fraction of tiles that execute it (2^-h for h
+ *                      control positions outside the tile)
+ *   QS_OPC_DISPATCH    fetched operations that move no data on a tile: uniform
+ *                      exchanges (relabels) and skipped conditional operations
+ *   QS_OPC_PLAIN_*     one-gate launches by gate kind
+ *   QS_OPC_MOVE        data-movement launches, QS_OPC_MOVE_FRACTION the sum
+ *                      of the fractions of amplitudes they move
+ * Writes min(cap, QS_OPC_COUNT) entries. */
+enum {
+    QS_OPC_TILE_PASS = 0,
+    QS_OPC_U = 1,          /* one-qubit 2x2 without in-tile controls */
+    QS_OPC_U_CTRL = 2,     /* controlled 2x2 with in-tile controls */
+    QS_OPC_X_REG = 3,      /* exchange controlled by register bits */
+    QS_OPC_X_LANE = 4,     /* exchange controlled by thread bits */
+    QS_OPC_NEG = 5,        /* CZ sign flip */
+    QS_OPC_DIAG = 6,       /* diagonal one-qubit or controlled-diagonal gate */
+    QS_OPC_REMAP = 7,      /* register re-layout through LDS */
+    QS_OPC_DISPATCH = 8,
+    QS_OPC_PLAIN_U = 9,
+    QS_OPC_PLAIN_CU = 10,
+    QS_OPC_PLAIN_CX = 11,
+    QS_OPC_PLAIN_CZ = 12,
+    QS_OPC_MOVE = 13,
+    QS_OPC_MOVE_FRACTION = 14,
+    QS_OPC_COUNT = 15
+};
+qs_status qs_program_op_counts(const qs_program *p, double *out, int cap);
+
 /* Instruction list of the pass as int32 words: 0 v = ApplyGate(v) local;
  * 1 s_0..s_{n-1} = PermuteQubits(s); 2 v = ApplyGate(v) not local.
  * Writes up to cap words into buf (host) and the full length into *len. */

@@ -520,6 +520,64 @@ qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out)
     });
 }
 
+qs_status qs_program_op_counts(const qs_program *p, double *out, int cap)
+{
+    return guard([&] {
+        need(p != nullptr && (out != nullptr || cap <= 0), "NULL argument");
+        double c[QS_OPC_COUNT] = {};
+        const Program &P = p->p;
+        for (const Launch &L : P.launches) {
+            if (L.type == L_TILE) {
+                c[QS_OPC_TILE_PASS] += 1;
+                for (int i = 0; i < L.op_count; ++i) {
+                    const TileOp &o = P.ops[L.op_begin + i];
+                    if (o.kind == OP_REMAP) {
+                        c[QS_OPC_REMAP] += 1;
+                        continue;
+                    }
+                    const double w = std::ldexp(1.0, -__builtin_popcountll(o.hmask));
+                    const bool ctrl = (o.rmask | o.lmask) != 0;
+                    c[QS_OPC_DISPATCH] += 1.0 - w;
+                    switch (o.kind) {
+                    case OP_U:
+                        c[ctrl ? QS_OPC_U_CTRL : QS_OPC_U] += w;
+                        break;
+                    case OP_X:
+                        if (!ctrl)
+                            c[QS_OPC_DISPATCH] += w;
+                        else
+                            c[o.lmask ? QS_OPC_X_LANE : QS_OPC_X_REG] += w;
+                        break;
+                    case OP_NEG:
+                        c[QS_OPC_NEG] += w;
+                        break;
+                    default:
+                        c[QS_OPC_DIAG] += w;
+                        break;
+                    }
+                }
+            } else if (L.type == L_PLAIN) {
+                switch (L.gate.kind) {
+                case QS_GATE_U: c[QS_OPC_PLAIN_U] += 1; break;
+                case QS_GATE_CU: c[QS_OPC_PLAIN_CU] += 1; break;
+                case QS_GATE_CX: c[QS_OPC_PLAIN_CX] += 1; break;
+                default: c[QS_OPC_PLAIN_CZ] += 1; break;
+                }
+            } else {
+                c[QS_OPC_MOVE] += 1;
+                int moved = 0;
+                for (size_t q = 0; q < L.pi.size(); ++q)
+                    moved += L.pi[q] != (int)q;
+                // an exchange of m positions leaves the amplitudes whose moved
+                // bits are all equal in place
+                c[QS_OPC_MOVE_FRACTION] += moved ? 1.0 - std::ldexp(1.0, -(moved / 2)) : 0.0;
+            }
+        }
+        for (int i = 0; i < cap && i < QS_OPC_COUNT; ++i)
+            out[i] = c[i];
+    });
+}
+
 qs_status qs_program_instructions(const qs_program *p, int32_t *buf, int64_t cap, int64_t *len)
 {
     return guard([&] {

@@ -39,7 +39,7 @@ GATE_DTYPE = np.dtype([("kind", np.int32), ("q0", np.int32), ("q1", np.int32), (
 EXPORTS = [
     "qs_last_error", "qs_device_info", "qs_state_create", "qs_state_destroy", "qs_state_set_stream",
     "qs_state_info", "qs_state_set_basis", "qs_get_permutation", "qs_apply_gate", "qs_apply_gates",
-    "qs_permute_qubits", "qs_compile", "qs_program_destroy", "qs_program_get_stats",
+    "qs_permute_qubits", "qs_compile", "qs_program_destroy", "qs_program_get_stats", "qs_program_op_counts",
     "qs_program_instructions", "qs_run_program", "qs_run_circuit", "qs_read_amplitudes", "qs_read_state",
     "qs_expect_z", "qs_norm", "qs_fidelity", "qs_synchronize", "qs_profile_enable", "qs_profile_read",
     "qs_batch_create", "qs_batch_run", "qs_batch_results", "qs_batch_read_state", "qs_batch_get_stats",
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
                              ctypes.POINTER(qs_run_opts), ctypes.POINTER(_vp)]
     L.qs_program_destroy.argtypes = [_vp]
     L.qs_program_get_stats.argtypes = [_vp, ctypes.POINTER(qs_program_stats)]
+    L.qs_program_op_counts.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.qs_program_instructions.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
                                           ctypes.POINTER(ctypes.c_int64)]
     L.qs_run_program.argtypes = [_vp, _vp]
@@ -261,6 +262,17 @@ def qs_program_get_stats(h: int) -> dict:
     st = qs_program_stats()
     _chk(load().qs_program_get_stats(h, ctypes.byref(st)))
     return {f: getattr(st, f) for f, _ in qs_program_stats._fields_}
+
+
+OPC_NAMES = ["tile_pass", "u", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch", "plain_u",
+             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction"]
+
+
+def qs_program_op_counts(h: int) -> dict:
+    """Work of a compiled program by class (see qs_program_op_counts in qsim.h)."""
+    out = np.zeros(len(OPC_NAMES), dtype=np.float64)
+    _chk(load().qs_program_op_counts(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(OPC_NAMES)))
+    return dict(zip(OPC_NAMES, (float(v) for v in out)))
 
 
 def qs_program_instructions(h: int, n: int):
@@ -536,6 +548,9 @@ class Program:
 
     def stats(self) -> dict:
         return qs_program_get_stats(self.h)
+
+    def op_counts(self) -> dict:
+        return qs_program_op_counts(self.h)
 
     def instructions(self):
         return qs_program_instructions(self.h, self.n)

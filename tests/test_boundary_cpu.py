@@ -118,3 +118,34 @@ def test_compile_with_start_placement():
 def test_empty_circuit_compiles():
     P = Q.Program(np.zeros(0, dtype=Q.GATE_DTYPE), 8, "c64")
     assert P.stats()["n_gates"] == 0 and P.instructions() == []
+
+
+def test_op_counts_classify_tile_work():
+    """Work counts by class on the host: one pass, its U gates, exchanges by
+    where their control lives, and weights for conditional operations."""
+    n, k = 16, 10
+    g = make_gates([(KIND_U, q, -1, H) for q in range(3)] +
+                   [(KIND_CX, 15, 0, None)] +    # control outside the tile: half the tiles, a relabel
+                   [(KIND_CX, 1, 2, None)])      # in-tile control
+    P = Q.Program(g, n, "c128", form="pass", k_tile=k, max_swaps=1, pinned=0, perm_exec="relabel")
+    c = P.op_counts()
+    P.close()
+    assert c["tile_pass"] == 1 and c["u"] == 3 and c["remap"] >= 1
+    assert c["x_reg"] + c["x_lane"] == 1
+    assert c["dispatch"] == 1.0          # 0.5 skipped + 0.5 relabel
+    assert c["plain_u"] == 0 and c["move"] == 0
+    Pp = Q.Program(g, n, "c128", form="plain")
+    cp = Pp.op_counts()
+    Pp.close()
+    assert cp["plain_u"] == 3 and cp["plain_cx"] == 2 and cp["tile_pass"] == 0
+
+
+def test_cost_model_prediction_is_linear_in_counts():
+    from paper_2010_09746_amd.costmodel import TILE_CLASSES, CostModel
+    cm = CostModel("c128", n_cal=20)
+    cm.tile_costs[(10, 0)] = {c: 1.0 + i for i, c in enumerate(TILE_CLASSES)}
+    cm.launch_costs = dict(plain_u=2.0, plain_cu=3.0, plain_cx=1.5, plain_cz=1.0, move=0.0, move_fraction=4.0)
+    counts = {c: 0.0 for c in Q.OPC_NAMES}
+    counts.update(tile_pass=2, u=10, remap=3, plain_cx=4, move_fraction=0.5)
+    want = (2 * 1.0 + 10 * 2.0 + 3 * (1.0 + TILE_CLASSES.index("remap")) + 4 * 1.5 + 0.5 * 4.0) * 2 ** 4
+    assert abs(cm.predict_counts(counts, 24, 10, 0) - want) < 1e-9

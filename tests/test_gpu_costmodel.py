@@ -1,0 +1,39 @@
+"""The measured cost model: calibration on the device, predictions that rank
+clearly different pass parameters the way the device does."""
+
+import pytest
+
+from workloads import layered_circuit
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2010_09746_amd import costmodel  # noqa: E402
+
+
+def test_calibration_costs_are_positive_and_fit():
+    cm = costmodel.CostModel("c128", n_cal=22)
+    cm.calibrate([(10, 0)])
+    tc = cm.tile_costs[(10, 0)]
+    assert tc["tile_pass"] > 0 and tc["u"] > 0 and tc["remap"] > 0
+    assert cm.fit_residual[(10, 0)] < 0.25
+    assert all(v > 0 for k, v in cm.launch_costs.items() if k != "move")
+
+
+def test_model_orders_clear_choices_like_the_device():
+    n = 24
+    g = layered_circuit(n, 12, 20100946 + 11)
+    cm = costmodel.CostModel("c128", n_cal=22)
+    good = dict(k_tile=10, max_swaps=8, pinned=3, perm_exec="relabel", reg_bits=0)
+    poor = dict(k_tile=7, max_swaps=1, pinned=0, perm_exec="relabel", reg_bits=0)
+    cm.calibrate([(10, 0), (7, 0)])
+    pg, _ = cm.predict(g, n, **good)
+    pp, _ = cm.predict(g, n, **poor)
+    mg = costmodel.measure_ms(g, n, "c128", good)
+    mp = costmodel.measure_ms(g, n, "c128", poor)
+    assert pg < pp and mg < mp
+    # the prediction is within a factor of two of the measurement
+    assert 0.5 < pg / mg < 2.0
