@@ -51,6 +51,10 @@ def parse():
                          "known size, used to scale hardware byte counters)")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
+    ap.add_argument("--rate-sweep", default="",
+                    help="serve: comma-separated lower arrival rates, each run with --sweep-requests requests after "
+                         "the main trace (finds the load one GPU sustains)")
+    ap.add_argument("--sweep-requests", type=int, default=60)
     ap.add_argument("--form", default="pass",
                     choices=["pass", "precision", "batch", "serve", "kernels", "qft", "random-family", "costmodel"],
                     help="pass: the 30-qubit complex128 workload (default line); precision: 32 qubits, complex64 "
@@ -209,6 +213,13 @@ def serve(a):
     res, rec = srv.serve(reqs, realtime=True, log=lambda m: print("serve " + m, file=sys.stderr, flush=True))
     st = latency_summary(rec)
     nerr = [abs(res[r["id"]]["norm"] - 1.0) for r in reqs]
+    main_stats = dict(srv.last_stats)
+    sweep = []
+    for rate in [float(x) for x in a.rate_sweep.split(",") if x.strip()]:
+        tr = request_trace(count=a.sweep_requests, rate=rate)
+        rq = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in tr]
+        _, rc = srv.serve(rq, realtime=True)
+        sweep.append(dict(rate=rate, requests=a.sweep_requests, **latency_summary(rc)))
     line = {
         "metric": "served p50/p99 latency", "value": st["p99_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": st["makespan_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -216,8 +227,9 @@ def serve(a):
         "config": {"workload": f"serving form: Poisson trace {a.requests} requests at {a.rate}/s, n uniform in "
                                f"[12,30], depth uniform in [20,100], complex64 with FP64 reductions, 200 GB budget, "
                                f"<Z_q> all q + 16 sampled amplitudes per request", "parallelism": "1 GPU"},
-        "latency": st, "server": srv.last_stats,
+        "latency": st, "server": main_stats,
         "max_norm_error": float(np.max(nerr)),
+        "rate_sweep": sweep,
     }
     srv.close()
     print(json.dumps(line), flush=True)

@@ -212,13 +212,25 @@ uint64_t phys_index(uint64_t i, const std::vector<int> &sigma)
 // pi[p] is bit p of x) as at most two in-place involutions: along each cycle
 // c_0 -> c_1 -> ... -> c_{L-1} of pi, first c_i -> c_{-i}, then c_i -> c_{1-i}
 // (indices mod L); the composition sends c_i to c_{i+1}.
+// Physical position p of the state moves to pi[p] (PermuteQubits, Section 2).
+//
+// The position map's cycles are grouped so that each group's positions, plus
+// the lowest positions (so that every load and store moves 128-byte runs), fit
+// a tile.  A group is one tile pass without gates that writes each tile back
+// with its bits permuted: the tile is closed under the map, so the move stays
+// inside the tile, in place, and every amplitude is read and written once.
+// Cycles too long for a tile go through two in-place involutions instead.
 void apply_position_map(qs_state *s, const std::vector<int> &pi)
 {
     const int n = s->n;
-    std::vector<int> r1(n), r2(n);
-    for (int p = 0; p < n; ++p)
-        r1[p] = r2[p] = p;
+    const int esize = elem_bytes(s->dt);
+    int low = 0;
+    while ((esize << low) < DIRECT_RUN_BYTES)
+        ++low;
+    const int max_k = std::min(n, esize == 16 ? 12 : 13);  // tiles of at most 64 KiB
+    std::vector<std::vector<int>> cycles;
     std::vector<char> seen(n, 0);
+    size_t longest = 0;
     for (int p = 0; p < n; ++p) {
         if (seen[p])
             continue;
@@ -227,6 +239,86 @@ void apply_position_map(qs_state *s, const std::vector<int> &pi)
             seen[x] = 1;
             cyc.push_back(x);
         }
+        if (cyc.size() > 1) {
+            longest = std::max(longest, cyc.size());
+            cycles.push_back(cyc);
+        }
+    }
+    if (cycles.empty())
+        return;
+    auto tile_bits = [&](const std::vector<int> &moved) {
+        std::vector<char> in(n, 0);
+        for (int p : moved)
+            in[p] = 1;
+        int k = (int)moved.size();
+        for (int p = 0; p < n && (p < low || k < MIN_TILE_BITS); ++p)
+            if (!in[p]) {
+                in[p] = 1;
+                ++k;
+            }
+        return k;
+    };
+    if (n >= MIN_TILE_BITS && (int)longest + low <= max_k) {
+        std::vector<std::vector<int>> groups;
+        for (const auto &c : cycles) {
+            bool placed = false;
+            for (auto &g : groups) {
+                std::vector<int> t = g;
+                t.insert(t.end(), c.begin(), c.end());
+                if (tile_bits(t) <= max_k) {
+                    g = t;
+                    placed = true;
+                    break;
+                }
+            }
+            if (!placed)
+                groups.push_back(c);
+        }
+        for (const auto &g : groups) {
+            std::vector<char> in(n, 0);
+            for (int p : g)
+                in[p] = 1;
+            std::vector<int> pos = g;
+            for (int p = 0; p < n && (p < low || (int)pos.size() < MIN_TILE_BITS); ++p)
+                if (!in[p]) {
+                    in[p] = 1;
+                    pos.push_back(p);
+                }
+            std::sort(pos.begin(), pos.end());
+            const int k = (int)pos.size();
+            int log_r = 0, log_nt = 0;
+            tile_shape(k, s->dt, 0, &log_r, &log_nt);
+            TileArgs a{};
+            tile_args_for_positions(pos, log_nt, log_r, a);
+            std::vector<int> tb(n, -1);
+            for (int b = 0; b < k; ++b)
+                tb[pos[b]] = b;
+            // this group's cycles only; the padding positions stay (another
+            // group may move them in its own pass)
+            std::vector<char> mine(n, 0);
+            for (int p : g)
+                mine[p] = 1;
+            for (int b = 0; b < k; ++b)
+                a.sperm[b] = (uint8_t)(mine[pos[b]] ? tb[pi[pos[b]]] : b);
+            a.io = 4u;
+            a.state = s->buf;
+            a.ops = nullptr;
+            a.n_ops = 0;
+            a.n_hi = n - k;
+            const uint64_t tiles = 1ull << (n - k);
+            timed(s->stream, P_MOVE, 2.0 * (double)s->bytes, [&] {
+                if (s->dt == QS_C64)
+                    launch_tile_f32(a, tiles, log_r, log_nt, s->stream);
+                else
+                    launch_tile_f64(a, tiles, log_r, log_nt, s->stream);
+            });
+        }
+        return;
+    }
+    std::vector<int> r1(n), r2(n);
+    for (int p = 0; p < n; ++p)
+        r1[p] = r2[p] = p;
+    for (const auto &cyc : cycles) {
         const int L = (int)cyc.size();
         for (int i = 0; i < L; ++i) {
             r1[cyc[i]] = cyc[((-i) % L + L) % L];

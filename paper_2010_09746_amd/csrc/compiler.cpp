@@ -607,17 +607,24 @@ void tile_args_from_launch(const Launch &L, TileArgs &a)
     }
 }
 
-void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a)
+void tile_args_for_positions(const std::vector<int> &pos, int log_nt, int log_r, TileArgs &a)
 {
     Launch L;
     L.type = L_TILE;
-    L.k = k;
+    L.k = (int)pos.size();
     L.log_nt = log_nt;
     L.log_r = log_r;
-    for (int b = 0; b < k; ++b)
-        L.pos.push_back(b);
+    L.pos = pos;
     set_direct_io(L, {}, QS_C128);
     tile_args_from_launch(L, a);
+}
+
+void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a)
+{
+    std::vector<int> pos(k);
+    for (int b = 0; b < k; ++b)
+        pos[b] = b;
+    tile_args_for_positions(pos, log_nt, log_r, a);
 }
 
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0_in,

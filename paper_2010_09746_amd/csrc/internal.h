@@ -86,10 +86,13 @@ struct TileArgs {
     uint32_t io;                  // bit 0: the load layout is that of ops[0] (an OP_REMAP, then
                                   // skipped), else tile-local index j * NT + tid;
                                   // bit 1: the store layout is that of the last OP_REMAP, else
-                                  // tile-local index j * NT + tid reached through LDS
+                                  // tile-local index j * NT + tid reached through LDS;
+                                  // bit 2 (only with no ops): the amplitude at tile-local index
+                                  // t is stored at index sperm(t) (a bit permutation)
     int32_t pad;
+    uint8_t sperm[16];            // tile bit b moves to tile bit sperm[b] (io bit 2)
 };
-static_assert(sizeof(TileArgs) == 96, "TileArgs layout");
+static_assert(sizeof(TileArgs) == 112, "TileArgs layout");
 
 // ---------------------------------------------------------------------------
 // batching form: one persistent launch over many circuits
@@ -180,8 +183,10 @@ namespace qsim {
 // kernel arguments of a tile launch: op count, positions and load/store
 // layouts (the state and ops pointers and n_hi are the caller's)
 void tile_args_from_launch(const Launch &L, TileArgs &a);
-// kernel arguments of an empty tile pass over tile positions 0..k-1
+// kernel arguments of an empty tile pass over tile positions 0..k-1, or over
+// the given ascending positions
 void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a);
+void tile_args_for_positions(const std::vector<int> &pos, int log_nt, int log_r, TileArgs &a);
 
 // choose register bits / threads for a tile of k bits
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);

@@ -327,7 +327,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 tbase = lane_bits(ops[0].hbit, tid);
                 have = true;
                 oi = 1;
-            } else {
+            } else if (n_ops > 0) {
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
                     *reinterpret_cast<C *>(lds + (tid + j * NT) * CB) = v[j];
@@ -423,7 +423,21 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
             // Store.  Direct: slot j holds pattern j ^ fl of the last layout,
             // whose offset is the slot's offset XOR the flipped bits' offset.
             const bool direct = have && dstore;
-            if (have && !dstore) {
+            if (a.io & 4u) {
+                // bit permutation of the tile (no ops ran, so v is in tile-index
+                // order j * NT + tid): the permutation is linear, so a lane part
+                // and per-slot parts are XORed
+                uint32_t pl = 0;
+#pragma unroll
+                for (int i = 0; i < LOG_NT; ++i)
+                    pl |= ((tid >> i) & 1u) << a.sperm[i];
+                for_slots<uint32_t>([&](int s) { return 1u << a.sperm[LOG_NT + s]; },
+                                    [&](int j, uint32_t o) { *reinterpret_cast<C *>(lds + (pl ^ o) * CB) = v[j]; });
+                lds_sync();
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    v[j] = *reinterpret_cast<const C *>(lds + (tid + j * NT) * CB);
+            } else if (have && !dstore) {
                 to_lds(lds, v, tbase, regs, fl);
                 lds_sync();
 #pragma unroll

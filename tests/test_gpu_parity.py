@@ -278,3 +278,29 @@ def test_precision_c128_oracle_28_qubits():
     st = Q.State(n, "c128").run(g, form="pass", k_tile=10, max_swaps=8, perm_exec="relabel", pinned=3)
     assert np.abs(st.amplitudes(idx) - ref[idx.astype(np.int64)]).max() <= 1e-12
     assert np.abs(st.expect_z() - O.expect_z(ref, n)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("pairs", [1, 3, 7])
+def test_permute_position_exchanges_bit_exact(dt, pairs):
+    """Position exchanges (i <-> n-1-i) as tile passes: with 7 pairs the map
+    needs two tile groups, and the second group's padding positions are moved
+    by the first."""
+    n = 18
+    _say(f"permute exchanges {dt} pairs={pairs}")
+    g = mixed_circuit(n, 30, seed=31)
+    st = Q.State(n, dt)
+    st.apply_gates(g)
+    base = st.to_numpy()
+    new = list(range(n))
+    for i in range(pairs):
+        new[i], new[n - 1 - i] = new[n - 1 - i], new[i]
+    st.permute(new)
+    assert np.array_equal(st.to_numpy(), base)
+    f = torch.float64 if dt == "c128" else torch.float32
+    raw = st.buffer.view(f).cpu().numpy().astype(np.float64)
+    phys = raw[0::2] + 1j * raw[1::2]
+    assert np.array_equal(phys, O.permute(base, n, list(range(n)), new))
+    st.permute(list(range(n)))
+    raw = st.buffer.view(f).cpu().numpy().astype(np.float64)
+    assert np.array_equal(raw[0::2] + 1j * raw[1::2], base)
