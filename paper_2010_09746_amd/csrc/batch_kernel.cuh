@@ -23,7 +23,7 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_batch(BatchArgs b)
         const uint32_t pi = items[it].pass, t0 = items[it].t0, t1 = items[it].t1;
         const auto &P = passes[pi];
         typename TK::Readout ro{P.last ? b.partials + 2 * (P.part + t0) : nullptr, P.zpos};
-        TK::template run_range<false>(P.t, lds_raw, t0, t1, 1, ro);
+        TK::template run_range<true>(P.t, lds_raw, t0, t1, 1, ro);
     }
 }
 

@@ -280,7 +280,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
 
     // Tiles t_first, t_first + t_step, ... below t_end.  A is TileArgs, read
     // from kernel arguments or from device memory.
-    template <bool OPF, typename A>
+    template <bool PF, typename A>
     static __device__ __forceinline__ void run_range(const A &a, unsigned char *lds, uint64_t t_first, uint64_t t_end,
                                                      uint64_t t_step, Readout ro)
     {
@@ -305,17 +305,22 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
             const C *src = st + tile_base(a, tile) + lane_ld;
             for_slots<uint64_t>(pbit_ld, [&](int j, uint64_t o) { dst[j] = src[o]; });
         };
-        if (t_first < t_end)
-            load(v, t_first);
-        // wait for the first tile here, so that the loop's own waits are only
-        // those for the prefetched tile (vmcnt(0): expcnt and lgkmcnt left at
-        // their maxima)
-        __builtin_amdgcn_s_waitcnt(0x0F70);
+        if constexpr (PF) {
+            if (t_first < t_end)
+                load(v, t_first);
+            // wait for the first tile here, so that the loop's own waits are only
+            // those for the prefetched tile (vmcnt(0): expcnt and lgkmcnt left at
+            // their maxima)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
 
         for (uint64_t t = t_first; t < t_end; t += t_step) {
             C w[NR];
-            const bool more = t + t_step < t_end;
-            if (more)
+            const bool more = PF && t + t_step < t_end;
+            if constexpr (!PF) {
+                load(v, t);
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as above
+            } else if (more)
                 load(w, t + t_step);
             const uint64_t base = tile_base(a, t);
 
@@ -334,23 +339,11 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 lds_sync();
             }
 
-            // The fields of the next operation are loaded while the current one
-            // runs, so the scalar-load latency hides behind its arithmetic.
-            // With OPF the fields of the next operation are loaded while the
-            // current one runs.
-            OpV cur;
-            if constexpr (OPF)
-                cur = fetch(ops, oi < n_ops ? oi : 0);
             for (; oi < n_ops; ++oi) {
-                OpV nx;
-                if constexpr (OPF) {
-                    nx = fetch(ops, oi + 1 < n_ops ? oi + 1 : oi);
-                } else {
-                    cur = fetch(ops, oi);
-                    // issue all of the operation's scalar loads together, so
-                    // that one wait covers them
-                    __asm__ __volatile__("" ::"s"(cur.kind), "s"(cur.hmask), "s"(cur.m[0]), "s"(cur.m[7]));
-                }
+                const OpV cur = fetch(ops, oi);
+                // issue all of the operation's scalar loads together, so that
+                // one wait covers them
+                __asm__ __volatile__("" ::"s"(cur.kind), "s"(cur.hmask), "s"(cur.m[0]), "s"(cur.m[7]));
                 const int kind = cur.kind;
                 if (kind == OP_REMAP) {
                     if (have) {
@@ -416,8 +409,6 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                         }
                     }
                 }
-                if constexpr (OPF)
-                    cur = nx;
             }
 
             // Store.  Direct: slot j holds pattern j ^ fl of the last layout,
@@ -464,10 +455,12 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
             if (ro.out)
                 reduce_pair(nrm, z, ro.out + 2 * ((t - t_first) / t_step), reinterpret_cast<double *>(lds));
             lds_sync();  // the next tile reuses the LDS buffer
-            if (more) {
+            if constexpr (PF) {
+                if (more) {
 #pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    v[j] = w[j];
+                    for (int j = 0; j < NR; ++j)
+                        v[j] = w[j];
+                }
             }
         }
     }
@@ -497,23 +490,14 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
 };
 
 // One workgroup per group of tiles: workgroup b takes tiles b, b + G, ...
-#ifndef QSIM_TILE_PERSIST
-#define QSIM_TILE_PERSIST 0
-#endif
-#ifndef QSIM_TILE_OPF
-#define QSIM_TILE_OPF 0
-#endif
-
+// One workgroup per tile.  (A persistent grid that prefetches the next tile,
+// with or without staggered starts, measured slower: the hardware dispatcher
+// keeps more tiles in flight than a fixed grid does.)
 template <typename R, int LOG_NT, int LOG_R>
-__global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a, uint64_t n_tiles)
+__global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    if (QSIM_TILE_PERSIST)
-        TileKernel<R, LOG_NT, LOG_R>::template run_range<QSIM_TILE_OPF>(a, lds_raw, blockIdx.x, n_tiles, gridDim.x,
-                                                                        {nullptr, 0});
-    else
-        TileKernel<R, LOG_NT, LOG_R>::template run_range<QSIM_TILE_OPF>(a, lds_raw, blockIdx.x, blockIdx.x + 1, 1,
-                                                                        {nullptr, 0});
+    TileKernel<R, LOG_NT, LOG_R>::template run_range<false>(a, lds_raw, blockIdx.x, blockIdx.x + 1, 1, {nullptr, 0});
 }
 
 template <typename R, int LOG_NT, int LOG_R>
@@ -522,26 +506,19 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
     using C = typename Cx<R>::T;
     constexpr size_t bytes = sizeof(C) << (LOG_NT + LOG_R);
     const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>);
-    // launches above the default dynamic LDS limit need the attribute first;
-    // the grid is the number of workgroups the device holds at once
-    static int grid_cap = 0;
-    if (grid_cap == 0) {
-        if (bytes > 65536) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-            if (e != hipSuccess)
-                fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
-        }
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1 << LOG_NT, bytes) != hipSuccess)
-            fail(QS_ERR_HIP, "tile kernel occupancy query failed");
-        grid_cap = std::max(1, cus) * std::max(1, per_cu);
+    // launches above the default dynamic LDS limit need the attribute first
+    static bool attr_set = bytes <= 65536;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess)
+            fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
+        attr_set = true;
     }
-    const uint64_t grid = QSIM_TILE_PERSIST ? std::min<uint64_t>(n_tiles, (uint64_t)grid_cap) : n_tiles;
-    if (grid == 0)
+    if (n_tiles > 0x7fffffffull)
+        fail(QS_ERR_UNSUPPORTED, "too many tiles for one launch");
+    if (n_tiles == 0)
         return;
-    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)grid), dim3(1 << LOG_NT), bytes, st, a, n_tiles);
+    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)n_tiles), dim3(1 << LOG_NT), bytes, st, a);
     check_launch("tile pass");
 }
 
