@@ -231,11 +231,12 @@ def test_empty_circuit_and_identity_permutation():
 
 def test_config2_full_size_pass_vs_plain():
     n = 30
-    _say("config-2 full size: pass (k=12, r=8, relabel) vs plain")
+    # the launch configuration bench.py times (k = 11, r = 16, relabel, 3 pinned)
+    _say("config-2 full size: pass (k=11, r=16, relabel) vs plain")
     g = config_circuit(2)
     idx = config_samples(2)
     a = Q.State(n, "c128")
-    a.run(g, form="pass", k_tile=12, max_swaps=8, perm_exec="relabel", pinned=3)
+    a.run(g, form="pass", k_tile=11, max_swaps=16, perm_exec="relabel", pinned=3)
     za, amp_a, na = a.expect_z(), a.amplitudes(idx), a.norm()
     a.close()
     del a
