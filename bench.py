@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# MI355X vector FP64 (and FP32 without packed math): 256 CUs x 64 FMA lanes
+# x 2 flops x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+FLOPS_PER_AMP_1Q = 14  # one 2x2 complex update per amplitude: 2 complex products + 1 complex sum
 
 
 def parse():
@@ -219,7 +223,7 @@ def serve(a):
         tr = request_trace(count=a.sweep_requests, rate=rate)
         rq = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in tr]
         _, rc = srv.serve(rq, realtime=True)
-        sweep.append(dict(rate=rate, requests=a.sweep_requests, **latency_summary(rc)))
+        sweep.append(dict(rate=rate, **latency_summary(rc)))
     line = {
         "metric": "served p50/p99 latency", "value": st["p99_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": st["makespan_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -408,9 +412,18 @@ def main():
                     traffic = tj.get("bytes_per_launch", {}).get(key)
             except Exception:
                 traffic = None
-        roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                        traffic=traffic, kernel="k_tile", algorithmic_bytes_per_launch=per_launch,
-                        avg_ms=tile["avg_ms"], launches_per_step=tile["launches"] / a.steps)
+        # the tile pass is priced against both ceilings; the one whose floor is
+        # higher (the binding one) is reported, the other is kept beside it
+        n_1q = int(sum(1 for gk in gates["kind"] if gk == 0))
+        flops_per_launch = n_1q * float(1 << n) * FLOPS_PER_AMP_1Q / max(1.0, tile["launches"] / a.steps)
+        tflops = flops_per_launch / (tile["avg_ms"] * 1e-3) / 1e12
+        hbm = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                   algorithmic_bytes_per_launch=per_launch)
+        alu = dict(bound="alu", achieved=tflops, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                   frac=tflops / VALU_PEAK_TFLOPS, algorithmic_flops_per_launch=flops_per_launch)
+        main, other = (alu, hbm) if alu["frac"] > hbm["frac"] else (hbm, alu)
+        roofline = dict(main, traffic=traffic, kernel="k_tile", avg_ms=tile["avg_ms"],
+                        launches_per_step=tile["launches"] / a.steps, other_ceiling=other)
 
     cpu = None
     if a.cpu_seconds > 0:
