@@ -8,6 +8,8 @@
 // lines and both halves of each line are consumed by the same wavefront.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.cuh"
 #include "kernels.h"
 
@@ -28,15 +30,18 @@ template <typename R>
 __global__ __launch_bounds__(NT) void k_set_basis(typename Cx<R>::T *s, uint64_t N, uint64_t x)
 {
     using C = typename Cx<R>::T;
-    const uint64_t i0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t i = i0 + (uint64_t)u * NT;
-        if (i < N) {
-            C v;
-            v.x = i == x ? R(1) : R(0);
-            v.y = R(0);
-            s[i] = v;
+    // grid-stride over chunks of NT * UNR items (a launch is capped below 2^31 threads)
+    for (uint64_t chunk = (uint64_t)blockIdx.x * NT * UNR; chunk < N; chunk += (uint64_t)gridDim.x * NT * UNR) {
+        const uint64_t i0 = chunk + threadIdx.x;
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t i = i0 + (uint64_t)u * NT;
+            if (i < N) {
+                C v;
+                v.x = i == x ? R(1) : R(0);
+                v.y = R(0);
+                s[i] = v;
+            }
         }
     }
 }
@@ -47,30 +52,33 @@ __global__ __launch_bounds__(NT) void k_pair_u(typename Cx<R>::T *__restrict__ s
                                                int t, int c_lo, int c_hi, uint64_t cbit, Mat<R> m)
 {
     using C = typename Cx<R>::T;
-    const uint64_t p0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
-    C a[UNR], b[UNR];
-    uint64_t ii[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t p = p0 + (uint64_t)u * NT;
-        uint64_t i;
-        if (CTRL)
-            i = insert_zero(insert_zero(p, c_lo), c_hi) | cbit;
-        else
-            i = insert_zero(p, t);
-        ii[u] = i;
-        if (p < npairs) {
-            a[u] = s[i];
-            b[u] = s[i | (1ull << t)];
+    // grid-stride over chunks of NT * UNR items (a launch is capped below 2^31 threads)
+    for (uint64_t chunk = (uint64_t)blockIdx.x * NT * UNR; chunk < npairs; chunk += (uint64_t)gridDim.x * NT * UNR) {
+        const uint64_t p0 = chunk + threadIdx.x;
+        C a[UNR], b[UNR];
+        uint64_t ii[UNR];
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t p = p0 + (uint64_t)u * NT;
+            uint64_t i;
+            if (CTRL)
+                i = insert_zero(insert_zero(p, c_lo), c_hi) | cbit;
+            else
+                i = insert_zero(p, t);
+            ii[u] = i;
+            if (p < npairs) {
+                a[u] = s[i];
+                b[u] = s[i | (1ull << t)];
+            }
         }
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t p = p0 + (uint64_t)u * NT;
-        if (p < npairs) {
-            C x = a[u], y = b[u];
-            s[ii[u]] = m.row0(x, y);
-            s[ii[u] | (1ull << t)] = m.row1(x, y);
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t p = p0 + (uint64_t)u * NT;
+            if (p < npairs) {
+                C x = a[u], y = b[u];
+                s[ii[u]] = m.row0(x, y);
+                s[ii[u] | (1ull << t)] = m.row1(x, y);
+            }
         }
     }
 }
@@ -81,24 +89,27 @@ __global__ __launch_bounds__(NT) void k_cx(typename Cx<R>::T *__restrict__ s, ui
                                            int lo, int hi, uint64_t cbit)
 {
     using C = typename Cx<R>::T;
-    const uint64_t p0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
-    C a[UNR], b[UNR];
-    uint64_t ii[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t p = p0 + (uint64_t)u * NT;
-        ii[u] = insert_zero(insert_zero(p, lo), hi) | cbit;
-        if (p < nquads) {
-            a[u] = s[ii[u]];
-            b[u] = s[ii[u] | (1ull << t)];
+    // grid-stride over chunks of NT * UNR items (a launch is capped below 2^31 threads)
+    for (uint64_t chunk = (uint64_t)blockIdx.x * NT * UNR; chunk < nquads; chunk += (uint64_t)gridDim.x * NT * UNR) {
+        const uint64_t p0 = chunk + threadIdx.x;
+        C a[UNR], b[UNR];
+        uint64_t ii[UNR];
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t p = p0 + (uint64_t)u * NT;
+            ii[u] = insert_zero(insert_zero(p, lo), hi) | cbit;
+            if (p < nquads) {
+                a[u] = s[ii[u]];
+                b[u] = s[ii[u] | (1ull << t)];
+            }
         }
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t p = p0 + (uint64_t)u * NT;
-        if (p < nquads) {
-            s[ii[u]] = b[u];
-            s[ii[u] | (1ull << t)] = a[u];
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t p = p0 + (uint64_t)u * NT;
+            if (p < nquads) {
+                s[ii[u]] = b[u];
+                s[ii[u] | (1ull << t)] = a[u];
+            }
         }
     }
 }
@@ -109,24 +120,27 @@ __global__ __launch_bounds__(NT) void k_cz(typename Cx<R>::T *__restrict__ s, ui
                                            int hi, uint64_t both)
 {
     using C = typename Cx<R>::T;
-    const uint64_t p0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
-    C a[UNR];
-    uint64_t ii[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t p = p0 + (uint64_t)u * NT;
-        ii[u] = insert_zero(insert_zero(p, lo), hi) | both;
-        if (p < nquads)
-            a[u] = s[ii[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t p = p0 + (uint64_t)u * NT;
-        if (p < nquads) {
-            C v = a[u];
-            v.x = -v.x;
-            v.y = -v.y;
-            s[ii[u]] = v;
+    // grid-stride over chunks of NT * UNR items (a launch is capped below 2^31 threads)
+    for (uint64_t chunk = (uint64_t)blockIdx.x * NT * UNR; chunk < nquads; chunk += (uint64_t)gridDim.x * NT * UNR) {
+        const uint64_t p0 = chunk + threadIdx.x;
+        C a[UNR];
+        uint64_t ii[UNR];
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t p = p0 + (uint64_t)u * NT;
+            ii[u] = insert_zero(insert_zero(p, lo), hi) | both;
+            if (p < nquads)
+                a[u] = s[ii[u]];
+        }
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t p = p0 + (uint64_t)u * NT;
+            if (p < nquads) {
+                C v = a[u];
+                v.x = -v.x;
+                v.y = -v.y;
+                s[ii[u]] = v;
+            }
         }
     }
 }
@@ -145,29 +159,35 @@ __global__ __launch_bounds__(NT) void k_involution(typename Cx<R>::T *__restrict
                                                    Involution J)
 {
     using C = typename Cx<R>::T;
-    const uint64_t i0 = (uint64_t)blockIdx.x * NT * UNR + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-        uint64_t x = i0 + (uint64_t)u * NT;
-        if (x >= N)
-            continue;
-        uint64_t y = x & ~J.moved_mask;
-#pragma unroll
-        for (int k = 0; k < MAX_QUBITS; ++k)
-            if (k < J.n_moved)
-                y |= ((x >> J.from[k]) & 1ull) << J.to[k];
-        if (x < y) {
-            C a = s[x], b = s[y];
-            s[x] = b;
-            s[y] = a;
+    // grid-stride over chunks of NT * UNR items (a launch is capped below 2^31 threads)
+    for (uint64_t chunk = (uint64_t)blockIdx.x * NT * UNR; chunk < N; chunk += (uint64_t)gridDim.x * NT * UNR) {
+        const uint64_t i0 = chunk + threadIdx.x;
+    #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            uint64_t x = i0 + (uint64_t)u * NT;
+            if (x >= N)
+                continue;
+            uint64_t y = x & ~J.moved_mask;
+    #pragma unroll
+            for (int k = 0; k < MAX_QUBITS; ++k)
+                if (k < J.n_moved)
+                    y |= ((x >> J.from[k]) & 1ull) << J.to[k];
+            if (x < y) {
+                C a = s[x], b = s[y];
+                s[x] = b;
+                s[y] = a;
+            }
         }
+        (void)c0;
     }
-    (void)c0;
 }
 
+// blocks for items, at most 2^31 threads per launch (the kernels stride over
+// the rest)
 inline unsigned blocks_for(uint64_t items)
 {
     uint64_t b = (items + (uint64_t)NT * UNR - 1) / ((uint64_t)NT * UNR);
+    b = std::min<uint64_t>(b, (1ull << 31) / NT);
     return (unsigned)(b ? b : 1);
 }
 

@@ -171,17 +171,29 @@ __global__ __launch_bounds__(FT) void k_fid(const Cplx<Ra> *__restrict__ a, cons
     }
 }
 
-__global__ void k_fid_final(const double *part, uint64_t nblocks, double *out)
+// out[q] over the block partials: block q, thread t takes the blocks
+// b = t (mod 256) in order, then a fixed tree over the 256 thread results
+// (a sum for q < 4, a maximum for q = 4)
+__global__ __launch_bounds__(256) void k_fid_final(const double *part, uint64_t nblocks, double *out)
 {
-    const int q = threadIdx.x;
-    if (q >= 5)
-        return;
+    __shared__ double red[256];
+    const int q = blockIdx.x;
     double r = 0;
-    for (uint64_t b = 0; b < nblocks; ++b) {
+    for (uint64_t b = threadIdx.x; b < nblocks; b += 256) {
         const double v = part[b * 5 + q];
         r = q == 4 ? (v > r ? v : r) : r + v;
     }
-    out[q] = r;
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double x = red[threadIdx.x], y = red[threadIdx.x + w];
+            red[threadIdx.x] = q == 4 ? (y > x ? y : x) : x + y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[q] = red[0];
 }
 
 template <typename Ra, typename Rb>
@@ -192,7 +204,7 @@ void fid_t(const void *a, const void *b, int n, const IndexMap &m, double *work,
     hipLaunchKernelGGL((k_fid<Ra, Rb>), dim3((unsigned)nb), dim3(FT), 0, st, reinterpret_cast<const Cplx<Ra> *>(a),
                        reinterpret_cast<const Cplx<Rb> *>(b), N, m, work);
     check_launch("fidelity");
-    hipLaunchKernelGGL(k_fid_final, dim3(1), dim3(64), 0, st, work, nb, out);
+    hipLaunchKernelGGL(k_fid_final, dim3(5), dim3(256), 0, st, work, nb, out);
     check_launch("fidelity final");
 }
 

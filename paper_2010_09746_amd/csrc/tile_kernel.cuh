@@ -35,6 +35,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.cuh"
 
 namespace qsim {
@@ -489,15 +491,17 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     }
 };
 
-// One workgroup per group of tiles: workgroup b takes tiles b, b + G, ...
 // One workgroup per tile.  (A persistent grid that prefetches the next tile,
 // with or without staggered starts, measured slower: the hardware dispatcher
-// keeps more tiles in flight than a fixed grid does.)
+// keeps more tiles in flight than a fixed grid does.)  Tile index =
+// blockIdx.y * gridDim.x + blockIdx.x: a grid holds fewer than 2^32 threads
+// per dimension, so launches of more tiles use rows of workgroups.
 template <typename R, int LOG_NT, int LOG_R>
 __global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    TileKernel<R, LOG_NT, LOG_R>::template run_range<false>(a, lds_raw, blockIdx.x, blockIdx.x + 1, 1, {nullptr, 0});
+    const uint64_t t = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    TileKernel<R, LOG_NT, LOG_R>::template run_range<false>(a, lds_raw, t, t + 1, 1, {nullptr, 0});
 }
 
 template <typename R, int LOG_NT, int LOG_R>
@@ -514,11 +518,14 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
             fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
         attr_set = true;
     }
-    if (n_tiles > 0x7fffffffull)
-        fail(QS_ERR_UNSUPPORTED, "too many tiles for one launch");
     if (n_tiles == 0)
         return;
-    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)n_tiles), dim3(1 << LOG_NT), bytes, st, a);
+    // at most 2^31 threads per grid row; tile counts are powers of two
+    const uint64_t row = std::min<uint64_t>(n_tiles, (1ull << 31) >> LOG_NT);
+    if (n_tiles % row != 0 || n_tiles / row > 0xffffull)
+        fail(QS_ERR_UNSUPPORTED, "tile count does not fit one launch");
+    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R>), dim3((unsigned)row, (unsigned)(n_tiles / row)), dim3(1 << LOG_NT),
+                       bytes, st, a);
     check_launch("tile pass");
 }
 
