@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--dtype", default="c128")
     # the measured cost model's choice for the 30-qubit workload (bench.py --form costmodel)
-    ap.add_argument("--k", type=int, default=11)
+    ap.add_argument("--k", type=int, default=12)
     ap.add_argument("--r", type=int, default=16)
     ap.add_argument("--perm-exec", default="relabel")
     ap.add_argument("--pinned", type=int, default=3)

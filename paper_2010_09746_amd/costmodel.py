@@ -141,9 +141,10 @@ class CostModel:
         return self.tile_costs[(k, reg_bits)]
 
     def _log_r(self, k: int, reg_bits: int) -> int:
-        # the library's tile shape: 8 complex128 / 16 complex64 per thread by
-        # default, at most 1024 threads and at least one wavefront
-        lr = reg_bits if reg_bits > 0 else (3 if self.dtype == "c128" else 4)
+        # the library's tile shape of a pass: 16 amplitudes per thread by
+        # default (8 for complex128 below 2^11-amplitude tiles), at most 1024
+        # threads and at least one wavefront
+        lr = reg_bits if reg_bits > 0 else ((4 if k >= 11 else 3) if self.dtype == "c128" else 4)
         lr = max(min(lr, 5), k - 10)
         return max(min(lr, k - 6), 1)
 

@@ -31,7 +31,7 @@ template <typename R, int LOG_NT, int LOG_R>
 void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
 {
     using C = typename Cx<R>::T;
-    constexpr size_t bytes = sizeof(C) << (LOG_NT + LOG_R);
+    constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
     // launches above the default dynamic LDS limit need the attribute first
     static bool attr_set = bytes <= 65536;
     if (!attr_set) {

@@ -317,6 +317,16 @@ std::vector<Instr> run_pass(const qs_gate *g, int64_t ng, int n, int m, int r, i
 // ---------------------------------------------------------------------------
 // lowering
 
+int pass_reg_bits(int k, qs_dtype dt)
+{
+    // measured on MI355X (30 qubits, random layers): 16 complex128 amplitudes
+    // per thread from 2^11-amplitude tiles up, fewer registers below; 16
+    // complex64 amplitudes per thread
+    if (dt == QS_C128)
+        return k >= 11 ? 4 : 3;
+    return 4;
+}
+
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt)
 {
     // measured on MI355X: 8 complex128 or 16 complex64 amplitudes per thread
@@ -702,7 +712,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         const bool tiled = k >= MIN_TILE_BITS && (size_t(dt == QS_C64 ? 8 : 16) << k) <= MAX_TILE_BYTES;
         int log_r = 0, log_nt = 0;
         if (tiled)
-            tile_shape(k, dt, o.reg_bits, &log_r, &log_nt);
+            tile_shape(k, dt, o.reg_bits > 0 ? o.reg_bits : pass_reg_bits(k, dt), &log_r, &log_nt);
         std::vector<int> spass = p.sigma0;
         size_t i = 0;
         while (i < p.instrs.size()) {

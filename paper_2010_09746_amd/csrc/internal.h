@@ -190,6 +190,8 @@ void tile_args_for_positions(const std::vector<int> &pos, int log_nt, int log_r,
 
 // choose register bits / threads for a tile of k bits
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);
+// register bits of a tile pass of the permutation form when none are asked for
+int pass_reg_bits(int k, qs_dtype dt);
 
 // ---------------------------------------------------------------------------
 // error reporting

@@ -151,17 +151,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                                                       bool lp)
     {
         if (slot == S || S == LOG_R - 1) {
-            if (lm == 0) {
-                // register controls only: the exchange as a 2x2 with the X
-                // matrix on the selected pairs (exact: products with 0 and 1)
-                Mat<R> x;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    x.a[q] = (q == 2 || q == 4) ? (R)1 : (R)0;
-                bfly_c<S, false, false>(v, x, rm, rv, lp);
-            } else {
-                xswap_c<S>(v, rm, rv, lp);
-            }
+            xswap_c<S>(v, rm, rv, lp);
         } else if constexpr (S + 1 < LOG_R) {
             dispatch_x<S + 1>(slot, v, rm, lm, rv, lp);
         }
@@ -227,24 +217,65 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return base;
     }
 
-    // registers <-> LDS at the tile-local indices of the layout (tbase, regs, fl)
-    static __device__ __forceinline__ void to_lds(unsigned char *lds, const C (&v)[NR], uint32_t tbase, uint32_t regs,
+    // LDS holds one component (real or imaginary part) of the tile at a time:
+    // half the bytes of the tile, so that more workgroups fit a CU.  The
+    // read-out reduction needs 2 NT doubles.
+    static constexpr uint32_t RB = sizeof(R);
+    static constexpr uint32_t LDS_BYTES = (RB << K) > 16u * NT ? (RB << K) : 16u * NT;
+    // the plain layout: thread bits are tile bits 0..LOG_NT-1, slot bit s is
+    // tile bit LOG_NT + s
+    static constexpr uint32_t regs_plain()
+    {
+        uint32_t r = 0;
+        for (int s = 0; s < LOG_R; ++s)
+            r |= (uint32_t)(LOG_NT + s) << (4 * s);
+        return r;
+    }
+
+    template <int COMP> static __device__ __forceinline__ R &part(C &c)
+    {
+        if constexpr (COMP == 0)
+            return c.x;
+        else
+            return c.y;
+    }
+
+    // one component, registers <-> LDS at the tile-local indices of the
+    // layout (tbase, regs, fl)
+    template <int COMP>
+    static __device__ __forceinline__ void to_lds(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
                                                    uint32_t fl)
     {
-        const uint32_t tb = tbase * CB;
-        for_slots<uint32_t>([&](int s) { return CB << rbit(regs, s); }, [&](int j, uint32_t o) {
-            uint32_t fo = 0;  // the flipped slot bits of the pattern
+        const uint32_t tb = tbase * RB;
+        uint32_t fo = 0;  // the flipped slot bits of the pattern
 #pragma unroll
-            for (int s = 0; s < LOG_R; ++s)
-                fo ^= ((fl >> s) & 1u) ? (CB << rbit(regs, s)) : 0u;
-            *reinterpret_cast<C *>(lds + (tb | (o ^ fo))) = v[j];
+        for (int s = 0; s < LOG_R; ++s)
+            fo ^= ((fl >> s) & 1u) ? (RB << rbit(regs, s)) : 0u;
+        for_slots<uint32_t>([&](int s) { return RB << rbit(regs, s); }, [&](int j, uint32_t o) {
+            *reinterpret_cast<R *>(lds + (tb | (o ^ fo))) = part<COMP>(v[j]);
         });
     }
+    template <int COMP>
     static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs)
     {
-        const uint32_t tb = tbase * CB;
-        for_slots<uint32_t>([&](int s) { return CB << rbit(regs, s); },
-                            [&](int j, uint32_t o) { v[j] = *reinterpret_cast<const C *>(lds + (tb | o)); });
+        const uint32_t tb = tbase * RB;
+        for_slots<uint32_t>([&](int s) { return RB << rbit(regs, s); },
+                            [&](int j, uint32_t o) { part<COMP>(v[j]) = *reinterpret_cast<const R *>(lds + (tb | o)); });
+    }
+
+    // Re-layout (tbase, regs, fl) -> (tbase2, regs2, no flips) through LDS,
+    // one component per round.
+    static __device__ __forceinline__ void relayout(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
+                                                    uint32_t fl, uint32_t tbase2, uint32_t regs2)
+    {
+        to_lds<0>(lds, v, tbase, regs, fl);
+        lds_sync();
+        from_lds<0>(lds, v, tbase2, regs2);
+        lds_sync();
+        to_lds<1>(lds, v, tbase, regs, fl);
+        lds_sync();
+        from_lds<1>(lds, v, tbase2, regs2);
+        lds_sync();
     }
 
     using OpPtr = const __attribute__((address_space(4))) TileOp *;
@@ -326,7 +357,7 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 load(w, t + t_step);
             const uint64_t base = tile_base(a, t);
 
-            uint32_t regs = 0, tbase = 0, fl = 0, F = 0;
+            uint32_t regs = 0, tbase = 0, fl = 0;
             bool have = false;
             int oi = 0;
             if (dload) {
@@ -335,10 +366,10 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 have = true;
                 oi = 1;
             } else if (n_ops > 0) {
-#pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    *reinterpret_cast<C *>(lds + (tid + j * NT) * CB) = v[j];
-                lds_sync();
+                // loaded in the plain layout; the first OP_REMAP moves it
+                regs = regs_plain();
+                tbase = tid;
+                have = true;
             }
 
             for (; oi < n_ops; ++oi) {
@@ -348,17 +379,11 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 __asm__ __volatile__("" ::"s"(cur.kind), "s"(cur.hmask), "s"(cur.m[0]), "s"(cur.m[7]));
                 const int kind = cur.kind;
                 if (kind == OP_REMAP) {
-                    if (have) {
-                        to_lds(lds, v, tbase, regs, fl);
-                        lds_sync();
-                    }
-                    regs = cur.rmask;
-                    tbase = lane_bits(cur.hbit, tid);
-                    from_lds(lds, v, tbase, regs);
-                    lds_sync();
+                    const uint32_t regs2 = cur.rmask, tbase2 = lane_bits(cur.hbit, tid);
+                    relayout(lds, v, tbase, regs, fl, tbase2, regs2);
+                    regs = regs2;
+                    tbase = tbase2;
                     fl = 0;
-                    F = 0;
-                    have = true;
                 } else if ((base & cur.hmask) == cur.hmask) {
                     const uint32_t rm = cur.rmask, lm = cur.lmask;
                     const uint32_t rv = rm & ~fl;
@@ -373,7 +398,6 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                     } else if (kind == OP_X) {
                         if ((rm | lm) == 0) {
                             fl ^= 1u << slot;
-                            F ^= 1u << rbit(regs, slot);
                         } else {
                             dispatch_x(slot, v, rm, lm, rv, lp);
                         }
@@ -424,18 +448,22 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
 #pragma unroll
                 for (int i = 0; i < LOG_NT; ++i)
                     pl |= ((tid >> i) & 1u) << a.sperm[i];
+                // one component per round
                 for_slots<uint32_t>([&](int s) { return 1u << a.sperm[LOG_NT + s]; },
-                                    [&](int j, uint32_t o) { *reinterpret_cast<C *>(lds + (pl ^ o) * CB) = v[j]; });
+                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (pl ^ o) * RB) = v[j].x; });
                 lds_sync();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    v[j] = *reinterpret_cast<const C *>(lds + (tid + j * NT) * CB);
+                    v[j].x = *reinterpret_cast<const R *>(lds + (tid + j * NT) * RB);
+                lds_sync();
+                for_slots<uint32_t>([&](int s) { return 1u << a.sperm[LOG_NT + s]; },
+                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (pl ^ o) * RB) = v[j].y; });
+                lds_sync();
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    v[j].y = *reinterpret_cast<const R *>(lds + (tid + j * NT) * RB);
             } else if (have && !dstore) {
-                to_lds(lds, v, tbase, regs, fl);
-                lds_sync();
-#pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    v[j] = *reinterpret_cast<const C *>(lds + (tid + j * NT) * CB);
+                relayout(lds, v, tbase, regs, fl, tid, regs_plain());
             }
             uint64_t dfl = 0;
             if (direct) {
@@ -508,7 +536,7 @@ template <typename R, int LOG_NT, int LOG_R>
 void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
 {
     using C = typename Cx<R>::T;
-    constexpr size_t bytes = sizeof(C) << (LOG_NT + LOG_R);
+    constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
     const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>);
     // launches above the default dynamic LDS limit need the attribute first
     static bool attr_set = bytes <= 65536;
