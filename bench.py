@@ -60,11 +60,13 @@ def parse():
                          "the main trace (finds the load one GPU sustains)")
     ap.add_argument("--sweep-requests", type=int, default=60)
     ap.add_argument("--form", default="pass",
-                    choices=["pass", "precision", "batch", "serve", "kernels", "qft", "random-family", "costmodel"],
+                    choices=["pass", "precision", "batch", "serve", "kernels", "qft", "random-family", "costmodel",
+                             "ablation"],
                     help="pass: the 30-qubit complex128 workload (default line); precision: 32 qubits, complex64 "
                          "against complex128; batch / serve: the batching and serving forms; kernels: each "
                          "single-purpose kernel at 30 qubits; qft: QFT and QFT-like circuits; random-family: the "
-                         "paper's random family, plain against pass form")
+                         "paper's random family, plain against pass form; costmodel: the measured cost model's "
+                         "choice and ranking; ablation: r=1, r=0 (fusion without the pass) and tile sizes 10..14")
     return ap.parse_args()
 
 
@@ -281,6 +283,19 @@ def random_family(a):
                              f"pass form k={a.k} r={a.r} against one launch per gate"}, r)
 
 
+def ablation(a):
+    """The 30-qubit workload under Algorithm 1 as printed (r = 1), the bundled
+    pass over tile sizes 10..14 and fusion without the pass (r = 0)."""
+    from paper_2010_09746_amd import studies
+
+    r = studies.ablation_study(n=a.n, dtype=a.dtype, layers=a.layers, r=a.r, k_ref=a.k)
+    best = min(r["rows"], key=lambda x: x["ms"])
+    ref = next(x for x in r["rows"] if x["variant"] == "fusion without pass")
+    _study_line("pass speedup over fusion without the pass", ref["ms"] / best["ms"], "x", best["ms"],
+                {"workload": f"layered circuit n={a.n} {a.dtype}, {r['gates']} gates: r=0 and r=1 at k={a.k}, "
+                             f"r={a.r} at k=10..14; device time of one run each"}, r)
+
+
 def costmodel_form(a):
     """Measured cost model: predict every candidate (k, r, register bits) for
     the 30-qubit workload, run a spread of them, and report how well the
@@ -328,6 +343,8 @@ def main():
         return random_family(a)
     if a.form == "costmodel":
         return costmodel_form(a)
+    if a.form == "ablation":
+        return ablation(a)
     if a.form == "serve":
         return serve(a)
 

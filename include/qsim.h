@@ -82,10 +82,15 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *              QS_FORM_PASS: the pass of Section 3 with m = k_tile local
  *              (in-tile) qubits; each run of local gates becomes one fused tile
  *              pass over HBM.
- *   k_tile     tile qubits (7..14, at most n).  A tile is 2^k_tile amplitudes
- *              held by one workgroup.
+ *   k_tile     tile qubits (at most n).  A tile is 2^k_tile amplitudes held
+ *              by one workgroup; tile passes need 7 <= k_tile and a tile of at
+ *              most 256 KiB (k_tile <= 14 for complex128, 15 for complex64),
+ *              else the local gates run one launch each.
  *   max_swaps  r >= 1: local/global exchanges chained into one PermuteQubits.
- *              r = 1 with pinned = 0 is Algorithm 1 as printed.
+ *              r = 1 with pinned = 0 is Algorithm 1 as printed.  r = 0: no
+ *              PermuteQubits at all; runs of gates on the first k_tile
+ *              positions are fused and every other gate is one launch (the
+ *              fusion without the pass, for comparison).
  *   pinned     qubits at positions < pinned are never exchanged out.
  *   perm_exec  QS_PERM_MOVE: each PermuteQubits moves the amplitudes (in place)
  *              and tiles are contiguous.  QS_PERM_RELABEL: no data moves; each

@@ -134,7 +134,7 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
         const qs_batch_opts o = *opts;
         const int K = o.k_tile;
         const size_t eb = dt == QS_C64 ? 8 : 16;
-        if (K < MIN_TILE_BITS || (eb << K) > MAX_TILE_BYTES)
+        if (K < MIN_TILE_BITS || (eb << K) > MAX_BATCH_TILE_BYTES)
             fail(QS_ERR_ARG, "k_tile out of range for the batching form");
         for (int c = 0; c < count; ++c)
             if (n_qubits[c] < K || n_qubits[c] > MAX_QUBITS)

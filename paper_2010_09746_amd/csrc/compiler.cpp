@@ -693,8 +693,8 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         const int k = std::min(o.k_tile, n);
         if (k < 1)
             fail(QS_ERR_ARG, "k_tile must be >= 1");
-        if (o.max_swaps < 1)
-            fail(QS_ERR_ARG, "max_swaps must be >= 1");
+        if (o.max_swaps < 0)
+            fail(QS_ERR_ARG, "max_swaps must be >= 0");
         if (o.pinned < 0 || o.pinned > k)
             fail(QS_ERR_ARG, "pinned must be in [0, k_tile]");
         if (o.perm_exec != QS_PERM_MOVE && o.perm_exec != QS_PERM_RELABEL)

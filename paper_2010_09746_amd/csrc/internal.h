@@ -67,7 +67,8 @@ constexpr int MAX_TILE_BITS = 15;
 constexpr int MIN_TILE_BITS = 7;
 constexpr int MAX_QUBITS = 34;          // states
 constexpr int MAX_COMPILE_QUBITS = 63;  // host-only compilation
-constexpr size_t MAX_TILE_BYTES = 131072;   // LDS of one tile (per workgroup)
+constexpr size_t MAX_TILE_BYTES = 262144;   // one tile of a pass (LDS holds half of it)
+constexpr size_t MAX_BATCH_TILE_BYTES = 131072;  // one tile of the batching and serving forms
 constexpr int DIRECT_RUN_BYTES = 128;       // contiguous bytes a direct tile load or store keeps together
 
 // Kernel arguments of one tile pass, passed by value.  The load and store

@@ -194,7 +194,7 @@ qs_status qs_server_create(qs_dtype dt, const qs_batch_opts *opts, size_t hbm_bu
             fail(QS_ERR_ARG, "unknown dtype");
         *out = nullptr;
         const size_t eb = dt == QS_C64 ? 8 : 16;
-        if (opts->k_tile < MIN_TILE_BITS || (eb << opts->k_tile) > MAX_TILE_BYTES)
+        if (opts->k_tile < MIN_TILE_BITS || (eb << opts->k_tile) > MAX_BATCH_TILE_BYTES)
             fail(QS_ERR_ARG, "k_tile out of range");
         auto *s = new qs_server();
         try {

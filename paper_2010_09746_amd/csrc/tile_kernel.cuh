@@ -558,13 +558,13 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
 }
 
 // Dispatch over the instantiated shapes: 2^6..2^10 threads, 2..32 amplitudes
-// per thread, tile bytes within the LDS of one CU.
+// per thread, at most 128 KiB of LDS (half the tile).
 template <typename R>
 void launch_tile_t(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st)
 {
 #define QS_TILE_CASE(NTB, RB)                                          \
     if (log_nt == NTB && log_r == RB) {                                \
-        if constexpr ((sizeof(typename Cx<R>::T) << (NTB + RB)) <= 131072) { \
+        if constexpr (TileKernel<R, NTB, RB>::LDS_BYTES <= 131072) {    \
             launch_tile_inst<R, NTB, RB>(a, n_tiles, st);              \
             return;                                                    \
         }                                                              \

@@ -171,3 +171,32 @@ def random_family_study(n: int = 28, dtype: str = "c128", ps=(0.0, 0.1, 0.3, 0.5
                          comm_fraction_without_pass=_comm_fraction(gates, k)))
     st.close()
     return {"n": n, "dtype": dtype, "k_tile": k, "max_swaps": r, "rows": rows}
+
+
+def ablation_study(n: int = 30, dtype: str = "c128", layers: int = 40, reps: int = 1,
+                   ks=(10, 11, 12, 13, 14), r: int = 16, k_ref: int = 12) -> dict:
+    """The 30-qubit layered workload under the pass's variants: Algorithm 1 as
+    printed (r = 1, no pinned qubits; each PermuteQubits moves the data, so
+    tiles stay contiguous), r = 1 with 3 pinned positions and relabelled
+    placements, the fused pass with bundled exchanges (r = 16) over tile sizes
+    ks, and fusion without the pass (r = 0: gates on the first k positions
+    fused, every other gate one launch).  Device time of one run of the
+    compiled program each."""
+    from . import costmodel
+    from workloads import config_circuit
+
+    g = config_circuit(2, n=n, layers=layers)
+    variants = [("fusion without pass", dict(k_tile=k_ref, max_swaps=0, pinned=0, perm_exec="relabel")),
+                ("Algorithm 1 (r=1), moved", dict(k_tile=k_ref, max_swaps=1, pinned=0, perm_exec="move")),
+                ("r=1, 3 pinned, relabelled", dict(k_tile=k_ref, max_swaps=1, pinned=3, perm_exec="relabel"))]
+    variants += [(f"pass r={r} k={k}", dict(k_tile=k, max_swaps=r, pinned=3, perm_exec="relabel")) for k in ks]
+    rows = []
+    for name, o in variants:
+        prog = Q.Program(g, n, dtype, form="pass", **o)
+        stt = prog.stats()
+        prog.close()
+        ms = costmodel.measure_ms(g, n, dtype, o, reps=reps)
+        rows.append(dict(variant=name, opts=o, ms=ms, amp_updates_per_s=len(g) * float(1 << n) / (ms * 1e-3),
+                         n_perm=stt["n_perm"], n_global=stt["n_global"], n_tile_passes=stt["n_tile_passes"],
+                         n_plain=stt["n_plain"]))
+    return {"n": n, "dtype": dtype, "gates": int(len(g)), "rows": rows}

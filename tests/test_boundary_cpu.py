@@ -98,11 +98,36 @@ def test_compile_rejects_bad_input():
     with pytest.raises(Q.QsimError):
         Q.Program(make_gates([(KIND_U, 0, -1, H)]), 4, "c128", sigma0=[0, 1, 1, 2])
     with pytest.raises(Q.QsimError):
-        Q.Program(make_gates([(KIND_U, 0, -1, H)]), 4, "c128", max_swaps=0)
+        Q.Program(make_gates([(KIND_U, 0, -1, H)]), 4, "c128", max_swaps=-1)
     bad = make_gates([(KIND_U, 0, -1, H)])
     bad[0]["kind"] = 9
     with pytest.raises(Q.QsimError):
         Q.Program(bad, 4, "c128")
+
+
+def test_fusion_without_pass():
+    """r = 0: no PermuteQubits; a gate runs in a tile pass exactly when its
+    non-diagonal targets are among the first k positions (diagonal gates are
+    local anywhere), else on its own, and the program still computes the plain
+    result."""
+    n, k = 10, 6
+    g = mixed_circuit(n, 120, seed=7)
+    P = Q.Program(g, n, "c128", k_tile=k, max_swaps=0)
+    ins = P.instructions()
+    st = P.stats()
+    P.close()
+    assert {t for t, _ in ins} <= {"apply", "global"} and st["n_perm"] == 0
+    ref, _ = O.pass_ref(g, n, k, r=1)
+    local = {v for t, v in ref if t == "apply"}
+    for t, v in ins:
+        kind, q0, q1, u = int(g[v]["kind"]), int(g[v]["q0"]), int(g[v]["q1"]), g[v]["u"]
+        diagonal = kind == 2 or (kind != 1 and not np.any(u[2:6]))   # CZ, or U/CU with u01 = u10 = 0
+        targets = [] if diagonal else ([q0] if kind == KIND_U else [q1])
+        assert (t == "apply") == all(q < k for q in targets), (t, v)
+    assert sorted(v for _, v in ins) == list(range(len(g)))
+    v, sig = O.run_program(g, n, ins)
+    assert np.abs(O.to_logical(v, n, sig) - O.run(g, n)).max() < 1e-13
+    assert len(local) > sum(t == "apply" for t, _ in ins)  # the pass makes more gates local
 
 
 def test_compile_with_start_placement():

@@ -89,6 +89,27 @@ def test_pass_all_kinds_c128_move(k):
     _check(st, O.run(g, n), "c128")
 
 
+@pytest.mark.parametrize("dt,n,k,reg", [("c128", 16, 14, 0), ("c128", 16, 14, 5), ("c64", 17, 15, 0)])
+def test_pass_largest_tiles(dt, n, k, reg):
+    """Tiles of 256 KiB (LDS holds one component, 128 KiB)."""
+    _say(f"largest tiles {dt} n={n} k={k} reg={reg}")
+    g = mixed_circuit(n, 250, seed=11 + k)
+    st = Q.State(n, dt)
+    st.run(g, form="pass", k_tile=k, max_swaps=4, reg_bits=reg, pinned=3, perm_exec="relabel")
+    _check(st, O.run(g, n), dt)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_fusion_without_pass(dt):
+    """r = 0: local runs fused, every other gate one launch."""
+    n, k = 14, 9
+    _say(f"fusion without pass {dt}")
+    g = mixed_circuit(n, 300, seed=21)
+    st = Q.State(n, dt)
+    st.run(g, form="pass", k_tile=k, max_swaps=0)
+    _check(st, O.run(g, n), dt)
+
+
 def test_tile_is_whole_state():
     n = 10
     _say("tile = whole state")

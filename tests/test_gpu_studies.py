@@ -90,3 +90,16 @@ def test_kernel_sweep_small():
     assert all(x["gbs"] > 0 for x in r["plain_u_per_target"])
     assert [m["pairs"] for m in r["permute"]] == list(range(1, 9))
     assert r["zsum"]["launches"] == 1
+
+
+def test_ablation_study_small():
+    r = studies.ablation_study(n=16, layers=8, ks=(10, 14), k_ref=10, r=8)
+    rows = {x["variant"]: x for x in r["rows"]}
+    assert set(rows) == {"fusion without pass", "Algorithm 1 (r=1), moved", "r=1, 3 pinned, relabelled",
+                         "pass r=8 k=10", "pass r=8 k=14"}
+    nopass = rows["fusion without pass"]
+    assert nopass["n_perm"] == 0 and nopass["n_global"] > 0 and nopass["n_plain"] == nopass["n_global"]
+    alg1 = rows["Algorithm 1 (r=1), moved"]
+    assert alg1["n_perm"] > 0 and alg1["n_global"] == 0
+    assert rows["pass r=8 k=14"]["n_tile_passes"] >= 1
+    assert all(x["ms"] > 0 for x in r["rows"])
