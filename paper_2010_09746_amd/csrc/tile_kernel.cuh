@@ -240,27 +240,41 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
             return c.y;
     }
 
+    // LDS slot of tile-local index i: i with each higher group of 5 bits
+    // XORed into its low 5 bits.  The map is linear over GF(2) and
+    // invertible, so a layout's addresses stay XORs of per-thread and per-slot
+    // parts; lanes whose indices differ only in high bits (thread bits placed
+    // on high tile bits by a re-layout) land in different banks instead of
+    // one.
+    static __host__ __device__ __forceinline__ constexpr uint32_t swz(uint32_t i)
+    {
+        uint32_t r = i;
+        for (int s = 5; s < K; s += 5)
+            r ^= (i >> s) & 31u;
+        return r;
+    }
+
     // one component, registers <-> LDS at the tile-local indices of the
     // layout (tbase, regs, fl)
     template <int COMP>
     static __device__ __forceinline__ void to_lds(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
                                                    uint32_t fl)
     {
-        const uint32_t tb = tbase * RB;
+        const uint32_t tb = swz(tbase) * RB;
         uint32_t fo = 0;  // the flipped slot bits of the pattern
 #pragma unroll
         for (int s = 0; s < LOG_R; ++s)
-            fo ^= ((fl >> s) & 1u) ? (RB << rbit(regs, s)) : 0u;
-        for_slots<uint32_t>([&](int s) { return RB << rbit(regs, s); }, [&](int j, uint32_t o) {
-            *reinterpret_cast<R *>(lds + (tb | (o ^ fo))) = part<COMP>(v[j]);
+            fo ^= ((fl >> s) & 1u) ? swz(1u << rbit(regs, s)) * RB : 0u;
+        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; }, [&](int j, uint32_t o) {
+            *reinterpret_cast<R *>(lds + (tb ^ o ^ fo)) = part<COMP>(v[j]);
         });
     }
     template <int COMP>
     static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs)
     {
-        const uint32_t tb = tbase * RB;
-        for_slots<uint32_t>([&](int s) { return RB << rbit(regs, s); },
-                            [&](int j, uint32_t o) { part<COMP>(v[j]) = *reinterpret_cast<const R *>(lds + (tb | o)); });
+        const uint32_t tb = swz(tbase) * RB;
+        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; },
+                            [&](int j, uint32_t o) { part<COMP>(v[j]) = *reinterpret_cast<const R *>(lds + (tb ^ o)); });
     }
 
     // Re-layout (tbase, regs, fl) -> (tbase2, regs2, no flips) through LDS,
@@ -448,20 +462,21 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
 #pragma unroll
                 for (int i = 0; i < LOG_NT; ++i)
                     pl |= ((tid >> i) & 1u) << a.sperm[i];
-                // one component per round
-                for_slots<uint32_t>([&](int s) { return 1u << a.sperm[LOG_NT + s]; },
-                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (pl ^ o) * RB) = v[j].x; });
+                // one component per round; LDS slots as in to_lds
+                const uint32_t wl = swz(pl) * RB, rl = swz(tid) * RB;
+                for_slots<uint32_t>([&](int s) { return swz(1u << a.sperm[LOG_NT + s]) * RB; },
+                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (wl ^ o)) = v[j].x; });
                 lds_sync();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    v[j].x = *reinterpret_cast<const R *>(lds + (tid + j * NT) * RB);
+                    v[j].x = *reinterpret_cast<const R *>(lds + (rl ^ (swz((uint32_t)j << LOG_NT) * RB)));
                 lds_sync();
-                for_slots<uint32_t>([&](int s) { return 1u << a.sperm[LOG_NT + s]; },
-                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (pl ^ o) * RB) = v[j].y; });
+                for_slots<uint32_t>([&](int s) { return swz(1u << a.sperm[LOG_NT + s]) * RB; },
+                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (wl ^ o)) = v[j].y; });
                 lds_sync();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    v[j].y = *reinterpret_cast<const R *>(lds + (tid + j * NT) * RB);
+                    v[j].y = *reinterpret_cast<const R *>(lds + (rl ^ (swz((uint32_t)j << LOG_NT) * RB)));
             } else if (have && !dstore) {
                 relayout(lds, v, tbase, regs, fl, tid, regs_plain());
             }
