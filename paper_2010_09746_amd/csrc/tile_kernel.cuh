@@ -18,9 +18,12 @@
 //   HBM -> registers  straight into the layout of the first OP_REMAP when
 //                     the thread bits of that layout cover the lowest tile
 //                     bits (runs of at least 128 contiguous bytes); otherwise
-//                     into tile-local index j * NT + tid and through LDS
+//                     into the plain layout (tile-local index j * NT + tid),
+//                     which the first OP_REMAP moves
 //   LDS <-> registers each OP_REMAP writes the tile to LDS at its tile-local
-//                     indices and reads it back in the new layout
+//                     indices and reads it back in the new layout, one
+//                     component (real parts, then imaginary parts) per round,
+//                     so LDS holds half the tile
 //   gates             one-qubit updates and exchanges on register bits run
 //                     inside a thread.  A control on a register bit selects
 //                     register pairs by a test that is uniform over the
@@ -29,8 +32,9 @@
 //                     decides for the whole tile from its base index
 //   registers -> HBM  straight from the last layout when its thread bits
 //                     cover the lowest tile bits, else through LDS
-// While a tile is processed, the next tile of the workgroup is already being
-// loaded into a second register array.
+// The pass kernel runs one workgroup per tile; the batching form's persistent
+// workgroups load their next tile into a second register array while the
+// current one is processed.
 #pragma once
 
 #include <hip/hip_runtime.h>
