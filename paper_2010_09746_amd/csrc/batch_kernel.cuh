@@ -32,14 +32,17 @@ void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
 {
     using C = typename Cx<R>::T;
     constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
-    // launches above the default dynamic LDS limit need the attribute first
-    static bool attr_set = bytes <= 65536;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<R, LOG_NT, LOG_R>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess)
-            fail(QS_ERR_HIP, std::string("batch kernel attribute: ") + hipGetErrorString(e));
-        attr_set = true;
+    static bool checked = false;
+    if (!checked) {
+        const void *fn = reinterpret_cast<const void *>(&k_batch<R, LOG_NT, LOG_R>);
+        check_no_static_lds(fn, "batch kernel");
+        // launches above the default dynamic LDS limit need the attribute first
+        if (bytes > 65536) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess)
+                fail(QS_ERR_HIP, std::string("batch kernel attribute: ") + hipGetErrorString(e));
+        }
+        checked = true;
     }
     hipLaunchKernelGGL((k_batch<R, LOG_NT, LOG_R>), dim3(grid), dim3(1 << LOG_NT), bytes, st, b);
     check_launch("batch launch");

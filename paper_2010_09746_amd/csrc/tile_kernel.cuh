@@ -258,27 +258,37 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return r;
     }
 
+    // LDS address of the buffer.  The kernels that use TileKernel have no
+    // static LDS (checked at launch), so the buffer starts at LDS address 0
+    // and a byte offset below LDS_BYTES can be XORed into it instead of added
+    // (an address is then one XOR of a per-thread and a per-slot part).
+    using LR = __attribute__((address_space(3))) R;
+    static __device__ __forceinline__ uint32_t lds_base(const unsigned char *lds)
+    {
+        return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) unsigned char *)lds;
+    }
+    static __device__ __forceinline__ LR *at(uint32_t addr) { return (LR *)(uintptr_t)addr; }
+
     // one component, registers <-> LDS at the tile-local indices of the
     // layout (tbase, regs, fl)
     template <int COMP>
     static __device__ __forceinline__ void to_lds(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
                                                    uint32_t fl)
     {
-        const uint32_t tb = swz(tbase) * RB;
         uint32_t fo = 0;  // the flipped slot bits of the pattern
 #pragma unroll
         for (int s = 0; s < LOG_R; ++s)
             fo ^= ((fl >> s) & 1u) ? swz(1u << rbit(regs, s)) * RB : 0u;
-        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; }, [&](int j, uint32_t o) {
-            *reinterpret_cast<R *>(lds + (tb ^ o ^ fo)) = part<COMP>(v[j]);
-        });
+        const uint32_t tb = lds_base(lds) ^ (swz(tbase) * RB) ^ fo;
+        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; },
+                            [&](int j, uint32_t o) { *at(tb ^ o) = part<COMP>(v[j]); });
     }
     template <int COMP>
     static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs)
     {
-        const uint32_t tb = swz(tbase) * RB;
+        const uint32_t tb = lds_base(lds) ^ (swz(tbase) * RB);
         for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; },
-                            [&](int j, uint32_t o) { part<COMP>(v[j]) = *reinterpret_cast<const R *>(lds + (tb ^ o)); });
+                            [&](int j, uint32_t o) { part<COMP>(v[j]) = *at(tb ^ o); });
     }
 
     // Re-layout (tbase, regs, fl) -> (tbase2, regs2, no flips) through LDS,
@@ -467,20 +477,20 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
                 for (int i = 0; i < LOG_NT; ++i)
                     pl |= ((tid >> i) & 1u) << a.sperm[i];
                 // one component per round; LDS slots as in to_lds
-                const uint32_t wl = swz(pl) * RB, rl = swz(tid) * RB;
+                const uint32_t wl = lds_base(lds) ^ (swz(pl) * RB), rl = lds_base(lds) ^ (swz(tid) * RB);
                 for_slots<uint32_t>([&](int s) { return swz(1u << a.sperm[LOG_NT + s]) * RB; },
-                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (wl ^ o)) = v[j].x; });
+                                    [&](int j, uint32_t o) { *at(wl ^ o) = v[j].x; });
                 lds_sync();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    v[j].x = *reinterpret_cast<const R *>(lds + (rl ^ (swz((uint32_t)j << LOG_NT) * RB)));
+                    v[j].x = *at(rl ^ (swz((uint32_t)j << LOG_NT) * RB));
                 lds_sync();
                 for_slots<uint32_t>([&](int s) { return swz(1u << a.sperm[LOG_NT + s]) * RB; },
-                                    [&](int j, uint32_t o) { *reinterpret_cast<R *>(lds + (wl ^ o)) = v[j].y; });
+                                    [&](int j, uint32_t o) { *at(wl ^ o) = v[j].y; });
                 lds_sync();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    v[j].y = *reinterpret_cast<const R *>(lds + (rl ^ (swz((uint32_t)j << LOG_NT) * RB)));
+                    v[j].y = *at(rl ^ (swz((uint32_t)j << LOG_NT) * RB));
             } else if (have && !dstore) {
                 relayout(lds, v, tbase, regs, fl, tid, regs_plain());
             }
@@ -538,6 +548,18 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     }
 };
 
+// TileKernel XORs byte offsets into the LDS base address, which needs the
+// dynamic LDS buffer to start at LDS address 0: no static LDS in the kernel.
+inline void check_no_static_lds(const void *fn, const char *what)
+{
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess)
+        fail(QS_ERR_HIP, std::string(what) + " attributes: " + hipGetErrorString(e));
+    if (fa.sharedSizeBytes != 0)
+        fail(QS_ERR_UNSUPPORTED, std::string(what) + " has static LDS; its LDS addressing assumes none");
+}
+
 // One workgroup per tile.  (A persistent grid that prefetches the next tile,
 // with or without staggered starts, measured slower: the hardware dispatcher
 // keeps more tiles in flight than a fixed grid does.)  Tile index =
@@ -557,13 +579,16 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
     using C = typename Cx<R>::T;
     constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
     const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>);
-    // launches above the default dynamic LDS limit need the attribute first
-    static bool attr_set = bytes <= 65536;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess)
-            fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
-        attr_set = true;
+    static bool checked = false;
+    if (!checked) {
+        check_no_static_lds(fn, "tile kernel");
+        // launches above the default dynamic LDS limit need the attribute first
+        if (bytes > 65536) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess)
+                fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
+        }
+        checked = true;
     }
     if (n_tiles == 0)
         return;
