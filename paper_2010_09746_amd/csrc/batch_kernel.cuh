@@ -48,7 +48,7 @@ void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
     check_launch("batch launch");
 }
 
-// tile shapes of the batching form: 64 or 128 threads, 4..16 amplitudes each
+// tile shapes of the batching form: 64 to 256 threads, 4..16 amplitudes each
 template <typename R>
 void launch_batch_t(const BatchArgs &b, int log_r, int log_nt, int grid, hipStream_t st)
 {
@@ -63,6 +63,8 @@ void launch_batch_t(const BatchArgs &b, int log_r, int log_nt, int grid, hipStre
     QS_BATCH_CASE(7, 2)
     QS_BATCH_CASE(7, 3)
     QS_BATCH_CASE(7, 4)
+    QS_BATCH_CASE(8, 3)
+    QS_BATCH_CASE(8, 4)
 #undef QS_BATCH_CASE
     fail(QS_ERR_UNSUPPORTED, "batch tile shape not instantiated (log_nt=" + std::to_string(log_nt) +
                                  ", log_r=" + std::to_string(log_r) + ")");

@@ -26,7 +26,7 @@ from . import qsim as Q
 
 
 class Server:
-    def __init__(self, dtype="c64", k_tile=10, max_swaps=16, pinned=3, reg_bits=0, chunk=8, wg_per_cu=8,
+    def __init__(self, dtype="c64", k_tile=10, max_swaps=16, pinned=3, reg_bits=0, chunk=8, wg_per_cu=16,
                  hbm_budget=200e9, max_slots=256, max_samples=16, compile_workers=8):
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
