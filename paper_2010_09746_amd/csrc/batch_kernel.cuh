@@ -14,7 +14,9 @@ template <typename R, int LOG_NT, int LOG_R>
 __global__ __launch_bounds__(1 << LOG_NT) void k_batch(BatchArgs b)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    using TK = TileKernel<R, LOG_NT, LOG_R>;
+    // whole amplitudes per re-layout round: the persistent grid, not LDS,
+    // sets how many workgroups are resident
+    using TK = TileKernel<R, LOG_NT, LOG_R, false>;
     using PassPtr = const __attribute__((address_space(4))) BatchPass *;
     using ItemPtr = const __attribute__((address_space(4))) BatchItem *;
     PassPtr passes = (PassPtr)b.passes;
@@ -30,8 +32,7 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_batch(BatchArgs b)
 template <typename R, int LOG_NT, int LOG_R>
 void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
 {
-    using C = typename Cx<R>::T;
-    constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
+    constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R, false>::LDS_BYTES;
     static bool checked = false;
     if (!checked) {
         const void *fn = reinterpret_cast<const void *>(&k_batch<R, LOG_NT, LOG_R>);

@@ -40,12 +40,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.cuh"
 
 namespace qsim {
 
-template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
+template <typename R, int LOG_NT, int LOG_R, bool HALF = true> struct TileKernel {
     using C = typename Cx<R>::T;
     static constexpr int NT = 1 << LOG_NT, NR = 1 << LOG_R, K = LOG_NT + LOG_R;
     static constexpr uint32_t CB = sizeof(C);  // bytes per amplitude
@@ -224,8 +225,12 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     // LDS holds one component (real or imaginary part) of the tile at a time:
     // half the bytes of the tile, so that more workgroups fit a CU.  The
     // read-out reduction needs 2 NT doubles.
+    // With HALF a re-layout moves one component per round and LDS holds half
+    // the tile; otherwise one round moves whole amplitudes (fewer barriers,
+    // for kernels whose residency LDS does not limit).
     static constexpr uint32_t RB = sizeof(R);
-    static constexpr uint32_t LDS_BYTES = (RB << K) > 16u * NT ? (RB << K) : 16u * NT;
+    static constexpr uint32_t EB = HALF ? RB : CB;  // bytes per LDS element of a re-layout
+    static constexpr uint32_t LDS_BYTES = (EB << K) > 16u * NT ? (EB << K) : 16u * NT;
     // the plain layout: thread bits are tile bits 0..LOG_NT-1, slot bit s is
     // tile bit LOG_NT + s
     static constexpr uint32_t regs_plain()
@@ -236,12 +241,29 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         return r;
     }
 
-    template <int COMP> static __device__ __forceinline__ R &part(C &c)
+    // element COMP of an amplitude in LDS: 0 real part, 1 imaginary part, 2
+    // both (a two-element vector, one LDS access)
+    using V2 = R __attribute__((ext_vector_type(2)));
+    template <int COMP> static __device__ __forceinline__ void put(uint32_t addr, const C &c)
     {
         if constexpr (COMP == 0)
-            return c.x;
+            *at<R>(addr) = c.x;
+        else if constexpr (COMP == 1)
+            *at<R>(addr) = c.y;
         else
-            return c.y;
+            *at<V2>(addr) = V2{c.x, c.y};
+    }
+    template <int COMP> static __device__ __forceinline__ void get(uint32_t addr, C &c)
+    {
+        if constexpr (COMP == 0) {
+            c.x = *at<R>(addr);
+        } else if constexpr (COMP == 1) {
+            c.y = *at<R>(addr);
+        } else {
+            const V2 t = *at<V2>(addr);
+            c.x = t.x;
+            c.y = t.y;
+        }
     }
 
     // LDS slot of tile-local index i: i with each higher group of 5 bits
@@ -262,15 +284,17 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
     // static LDS (checked at launch), so the buffer starts at LDS address 0
     // and a byte offset below LDS_BYTES can be XORed into it instead of added
     // (an address is then one XOR of a per-thread and a per-slot part).
-    using LR = __attribute__((address_space(3))) R;
     static __device__ __forceinline__ uint32_t lds_base(const unsigned char *lds)
     {
         return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) unsigned char *)lds;
     }
-    static __device__ __forceinline__ LR *at(uint32_t addr) { return (LR *)(uintptr_t)addr; }
+    template <typename T = R> static __device__ __forceinline__ __attribute__((address_space(3))) T *at(uint32_t addr)
+    {
+        return (__attribute__((address_space(3))) T *)(uintptr_t)addr;
+    }
 
-    // one component, registers <-> LDS at the tile-local indices of the
-    // layout (tbase, regs, fl)
+    // element COMP of every amplitude, registers <-> LDS at the tile-local
+    // indices of the layout (tbase, regs, fl)
     template <int COMP>
     static __device__ __forceinline__ void to_lds(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
                                                    uint32_t fl)
@@ -278,32 +302,39 @@ template <typename R, int LOG_NT, int LOG_R> struct TileKernel {
         uint32_t fo = 0;  // the flipped slot bits of the pattern
 #pragma unroll
         for (int s = 0; s < LOG_R; ++s)
-            fo ^= ((fl >> s) & 1u) ? swz(1u << rbit(regs, s)) * RB : 0u;
-        const uint32_t tb = lds_base(lds) ^ (swz(tbase) * RB) ^ fo;
-        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; },
-                            [&](int j, uint32_t o) { *at(tb ^ o) = part<COMP>(v[j]); });
+            fo ^= ((fl >> s) & 1u) ? swz(1u << rbit(regs, s)) * EB : 0u;
+        const uint32_t tb = lds_base(lds) ^ (swz(tbase) * EB) ^ fo;
+        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * EB; },
+                            [&](int j, uint32_t o) { put<COMP>(tb ^ o, v[j]); });
     }
     template <int COMP>
     static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs)
     {
-        const uint32_t tb = lds_base(lds) ^ (swz(tbase) * RB);
-        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * RB; },
-                            [&](int j, uint32_t o) { part<COMP>(v[j]) = *at(tb ^ o); });
+        const uint32_t tb = lds_base(lds) ^ (swz(tbase) * EB);
+        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * EB; },
+                            [&](int j, uint32_t o) { get<COMP>(tb ^ o, v[j]); });
     }
 
     // Re-layout (tbase, regs, fl) -> (tbase2, regs2, no flips) through LDS,
-    // one component per round.
+    // one component per round with HALF.
     static __device__ __forceinline__ void relayout(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
                                                     uint32_t fl, uint32_t tbase2, uint32_t regs2)
     {
-        to_lds<0>(lds, v, tbase, regs, fl);
-        lds_sync();
-        from_lds<0>(lds, v, tbase2, regs2);
-        lds_sync();
-        to_lds<1>(lds, v, tbase, regs, fl);
-        lds_sync();
-        from_lds<1>(lds, v, tbase2, regs2);
-        lds_sync();
+        if constexpr (HALF) {
+            to_lds<0>(lds, v, tbase, regs, fl);
+            lds_sync();
+            from_lds<0>(lds, v, tbase2, regs2);
+            lds_sync();
+            to_lds<1>(lds, v, tbase, regs, fl);
+            lds_sync();
+            from_lds<1>(lds, v, tbase2, regs2);
+            lds_sync();
+        } else {
+            to_lds<2>(lds, v, tbase, regs, fl);
+            lds_sync();
+            from_lds<2>(lds, v, tbase2, regs2);
+            lds_sync();
+        }
     }
 
     using OpPtr = const __attribute__((address_space(4))) TileOp *;
@@ -576,7 +607,6 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
 template <typename R, int LOG_NT, int LOG_R>
 void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
 {
-    using C = typename Cx<R>::T;
     constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
     const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>);
     static bool checked = false;
