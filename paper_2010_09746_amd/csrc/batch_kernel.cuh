@@ -33,8 +33,9 @@ template <typename R, int LOG_NT, int LOG_R>
 void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
 {
     constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R, false>::LDS_BYTES;
-    static bool checked = false;
-    if (!checked) {
+    // once per process (a thread-safe static initialisation); a failure
+    // throws, and the next launch tries again
+    static const bool ready = [] {
         const void *fn = reinterpret_cast<const void *>(&k_batch<R, LOG_NT, LOG_R>);
         check_no_static_lds(fn, "batch kernel");
         // launches above the default dynamic LDS limit need the attribute first
@@ -43,8 +44,9 @@ void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
             if (e != hipSuccess)
                 fail(QS_ERR_HIP, std::string("batch kernel attribute: ") + hipGetErrorString(e));
         }
-        checked = true;
-    }
+        return true;
+    }();
+    (void)ready;
     hipLaunchKernelGGL((k_batch<R, LOG_NT, LOG_R>), dim3(grid), dim3(1 << LOG_NT), bytes, st, b);
     check_launch("batch launch");
 }

@@ -609,8 +609,9 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
 {
     constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
     const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R>);
-    static bool checked = false;
-    if (!checked) {
+    // once per process (a thread-safe static initialisation); a failure
+    // throws, and the next launch tries again
+    static const bool ready = [fn] {
         check_no_static_lds(fn, "tile kernel");
         // launches above the default dynamic LDS limit need the attribute first
         if (bytes > 65536) {
@@ -618,8 +619,9 @@ void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
             if (e != hipSuccess)
                 fail(QS_ERR_HIP, std::string("tile kernel attribute: ") + hipGetErrorString(e));
         }
-        checked = true;
-    }
+        return true;
+    }();
+    (void)ready;
     if (n_tiles == 0)
         return;
     // at most 2^31 threads per grid row; tile counts are powers of two
