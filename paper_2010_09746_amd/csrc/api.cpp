@@ -300,7 +300,9 @@ void apply_position_map(qs_state *s, const std::vector<int> &pi)
                 mine[p] = 1;
             for (int b = 0; b < k; ++b)
                 a.sperm[b] = (uint8_t)(mine[pos[b]] ? tb[pi[pos[b]]] : b);
-            a.io = 4u;
+            // permuted store; the tile holds the lowest positions, so every
+            // load and store moves whole lines (streaming access)
+            a.io = 4u | 8u;
             a.state = s->buf;
             a.ops = nullptr;
             a.n_ops = 0;

@@ -15,8 +15,9 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_batch(BatchArgs b)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     // whole amplitudes per re-layout round: the persistent grid, not LDS,
-    // sets how many workgroups are resident
-    using TK = TileKernel<R, LOG_NT, LOG_R, false>;
+    // sets how many workgroups are resident; ordinary (cached) loads and
+    // stores: the states are small and are read again at the next level
+    using TK = TileKernel<R, LOG_NT, LOG_R, false, false>;
     using PassPtr = const __attribute__((address_space(4))) BatchPass *;
     using ItemPtr = const __attribute__((address_space(4))) BatchItem *;
     PassPtr passes = (PassPtr)b.passes;
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_batch(BatchArgs b)
 template <typename R, int LOG_NT, int LOG_R>
 void launch_batch_inst(const BatchArgs &b, int grid, hipStream_t st)
 {
-    constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R, false>::LDS_BYTES;
+    constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R, false, false>::LDS_BYTES;
     // once per process (a thread-safe static initialisation); a failure
     // throws, and the next launch tries again
     static const bool ready = [] {

@@ -71,6 +71,22 @@ template <typename R> struct Mat {
     }
 };
 
+// Streaming access to one amplitude: non-temporal loads and stores, for
+// kernels that read and write each amplitude once per launch over a state far
+// larger than the caches.
+template <typename C> __device__ __forceinline__ C ld_stream(const C *p)
+{
+    C v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    return v;
+}
+template <typename C> __device__ __forceinline__ void st_stream(C *p, const C &v)
+{
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 inline void check_launch(const char *what)
 {
     hipError_t e = hipGetLastError();

@@ -579,7 +579,7 @@ void set_direct_io(Launch &L, const std::vector<TileOp> &ops, qs_dtype dt)
         for (int s = 0; s < L.log_r; ++s)
             reg[s] = (uint8_t)L.pos[L.log_nt + s];
     };
-    L.io = 0;
+    L.io = contiguous ? 8u : 0u;
     plain(L.ld_lane, L.ld_reg);
     plain(L.st_lane, L.st_reg);
     const TileOp *o = ops.data() + L.op_begin;

@@ -17,6 +17,26 @@ namespace qsim {
 
 namespace {
 
+// Amplitude access: non-temporal when every 128-byte line a launch touches is
+// read or written whole by one instruction (no qubit below the line size is
+// split across instructions), cached otherwise, where the two halves of a line
+// arrive from different instructions and the cache merges them.
+template <bool NTA, typename C> __device__ __forceinline__ C ld(const C *p)
+{
+    if constexpr (NTA)
+        return ld_stream(p);
+    else
+        return *p;
+}
+template <bool NTA, typename C> __device__ __forceinline__ void st(C *p, const C &v)
+{
+    if constexpr (NTA)
+        st_stream(p, v);
+    else
+        *p = v;
+}
+
+
 constexpr int NT = 256;   // threads per block
 constexpr int UNR = 4;    // pairs per thread, loads issued before use
 
@@ -40,14 +60,14 @@ __global__ __launch_bounds__(NT) void k_set_basis(typename Cx<R>::T *s, uint64_t
                 C v;
                 v.x = i == x ? R(1) : R(0);
                 v.y = R(0);
-                s[i] = v;
+                st_stream(&s[i], v);
             }
         }
     }
 }
 
 // (a_i, a_j) <- U (a_i, a_j) for j = i | 2^t, optionally only where bit c = 1.
-template <typename R, bool CTRL>
+template <typename R, bool CTRL, bool NTA>
 __global__ __launch_bounds__(NT) void k_pair_u(typename Cx<R>::T *__restrict__ s, uint64_t npairs,
                                                int t, int c_lo, int c_hi, uint64_t cbit, Mat<R> m)
 {
@@ -67,8 +87,8 @@ __global__ __launch_bounds__(NT) void k_pair_u(typename Cx<R>::T *__restrict__ s
                 i = insert_zero(p, t);
             ii[u] = i;
             if (p < npairs) {
-                a[u] = s[i];
-                b[u] = s[i | (1ull << t)];
+                a[u] = ld<NTA>(&s[i]);
+                b[u] = ld<NTA>(&s[i | (1ull << t)]);
             }
         }
     #pragma unroll
@@ -76,15 +96,15 @@ __global__ __launch_bounds__(NT) void k_pair_u(typename Cx<R>::T *__restrict__ s
             uint64_t p = p0 + (uint64_t)u * NT;
             if (p < npairs) {
                 C x = a[u], y = b[u];
-                s[ii[u]] = m.row0(x, y);
-                s[ii[u] | (1ull << t)] = m.row1(x, y);
+                st<NTA>(&s[ii[u]], m.row0(x, y));
+                st<NTA>(&s[ii[u] | (1ull << t)], m.row1(x, y));
             }
         }
     }
 }
 
 // controlled X: exchange a_i and a_j where bit c = 1
-template <typename R>
+template <typename R, bool NTA>
 __global__ __launch_bounds__(NT) void k_cx(typename Cx<R>::T *__restrict__ s, uint64_t nquads, int t,
                                            int lo, int hi, uint64_t cbit)
 {
@@ -99,23 +119,23 @@ __global__ __launch_bounds__(NT) void k_cx(typename Cx<R>::T *__restrict__ s, ui
             uint64_t p = p0 + (uint64_t)u * NT;
             ii[u] = insert_zero(insert_zero(p, lo), hi) | cbit;
             if (p < nquads) {
-                a[u] = s[ii[u]];
-                b[u] = s[ii[u] | (1ull << t)];
+                a[u] = ld<NTA>(&s[ii[u]]);
+                b[u] = ld<NTA>(&s[ii[u] | (1ull << t)]);
             }
         }
     #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             uint64_t p = p0 + (uint64_t)u * NT;
             if (p < nquads) {
-                s[ii[u]] = b[u];
-                s[ii[u] | (1ull << t)] = a[u];
+                st<NTA>(&s[ii[u]], b[u]);
+                st<NTA>(&s[ii[u] | (1ull << t)], a[u]);
             }
         }
     }
 }
 
 // controlled Z: negate a_i where both bits are 1
-template <typename R>
+template <typename R, bool NTA>
 __global__ __launch_bounds__(NT) void k_cz(typename Cx<R>::T *__restrict__ s, uint64_t nquads, int lo,
                                            int hi, uint64_t both)
 {
@@ -130,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_cz(typename Cx<R>::T *__restrict__ s, ui
             uint64_t p = p0 + (uint64_t)u * NT;
             ii[u] = insert_zero(insert_zero(p, lo), hi) | both;
             if (p < nquads)
-                a[u] = s[ii[u]];
+                a[u] = ld<NTA>(&s[ii[u]]);
         }
     #pragma unroll
         for (int u = 0; u < UNR; ++u) {
@@ -139,7 +159,7 @@ __global__ __launch_bounds__(NT) void k_cz(typename Cx<R>::T *__restrict__ s, ui
                 C v = a[u];
                 v.x = -v.x;
                 v.y = -v.y;
-                s[ii[u]] = v;
+                st<NTA>(&s[ii[u]], v);
             }
         }
     }
@@ -154,7 +174,7 @@ struct Involution {
     uint64_t moved_mask;
 };
 
-template <typename R>
+template <typename R, bool NTA>
 __global__ __launch_bounds__(NT) void k_involution(typename Cx<R>::T *__restrict__ s, uint64_t N, int c0,
                                                    Involution J)
 {
@@ -173,9 +193,9 @@ __global__ __launch_bounds__(NT) void k_involution(typename Cx<R>::T *__restrict
                 if (k < J.n_moved)
                     y |= ((x >> J.from[k]) & 1ull) << J.to[k];
             if (x < y) {
-                C a = s[x], b = s[y];
-                s[x] = b;
-                s[y] = a;
+                const C a = ld<NTA>(&s[x]), b = ld<NTA>(&s[y]);
+                st<NTA>(&s[x], b);
+                st<NTA>(&s[y], a);
             }
         }
         (void)c0;
@@ -191,35 +211,37 @@ inline unsigned blocks_for(uint64_t items)
     return (unsigned)(b ? b : 1);
 }
 
-template <typename R>
-void plain_gate_t(void *state, int n, const qs_gate &g, hipStream_t st)
+// qubits below this index split a 128-byte line
+template <typename R> constexpr int line_bits() { return sizeof(typename Cx<R>::T) == 16 ? 3 : 4; }
+
+template <typename R, bool NTA>
+void plain_gate_nt(typename Cx<R>::T *s, int n, const qs_gate &g, hipStream_t st)
 {
-    using C = typename Cx<R>::T;
-    C *s = reinterpret_cast<C *>(state);
     switch (g.kind) {
     case QS_GATE_U: {
         uint64_t np = 1ull << (n - 1);
-        hipLaunchKernelGGL((k_pair_u<R, false>), dim3(blocks_for(np)), dim3(NT), 0, st, s, np, g.q0, 0, 0,
+        hipLaunchKernelGGL((k_pair_u<R, false, NTA>), dim3(blocks_for(np)), dim3(NT), 0, st, s, np, g.q0, 0, 0,
                            0ull, Mat<R>(g.u));
         break;
     }
     case QS_GATE_CU: {
         uint64_t nq = 1ull << (n - 2);
         int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
-        hipLaunchKernelGGL((k_pair_u<R, true>), dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, g.q1, lo, hi,
+        hipLaunchKernelGGL((k_pair_u<R, true, NTA>), dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, g.q1, lo, hi,
                            1ull << g.q0, Mat<R>(g.u));
         break;
     }
     case QS_GATE_CX: {
         uint64_t nq = 1ull << (n - 2);
         int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
-        hipLaunchKernelGGL(k_cx<R>, dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, g.q1, lo, hi, 1ull << g.q0);
+        hipLaunchKernelGGL((k_cx<R, NTA>), dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, g.q1, lo, hi,
+                           1ull << g.q0);
         break;
     }
     case QS_GATE_CZ: {
         uint64_t nq = 1ull << (n - 2);
         int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
-        hipLaunchKernelGGL(k_cz<R>, dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, lo, hi,
+        hipLaunchKernelGGL((k_cz<R, NTA>), dim3(blocks_for(nq)), dim3(NT), 0, st, s, nq, lo, hi,
                            (1ull << g.q0) | (1ull << g.q1));
         break;
     }
@@ -227,6 +249,19 @@ void plain_gate_t(void *state, int n, const qs_gate &g, hipStream_t st)
         fail(QS_ERR_ARG, "unknown gate kind");
     }
     check_launch("plain gate");
+}
+
+template <typename R>
+void plain_gate_t(void *state, int n, const qs_gate &g, hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    C *s = reinterpret_cast<C *>(state);
+    // the lowest qubit the launch splits on: the target, or the lower of two
+    const int low = g.kind == QS_GATE_U ? g.q0 : (g.q0 < g.q1 ? g.q0 : g.q1);
+    if (low >= line_bits<R>())
+        plain_gate_nt<R, true>(s, n, g, st);
+    else
+        plain_gate_nt<R, false>(s, n, g, st);
 }
 
 }  // namespace
@@ -271,12 +306,20 @@ void launch_involution(void *state, qs_dtype dt, int n, const std::vector<int> &
     if (J.n_moved == 0)
         return;
     uint64_t N = 1ull << n;
-    if (dt == QS_C64)
-        hipLaunchKernelGGL(k_involution<float>, dim3(blocks_for(N)), dim3(NT), 0, st,
-                           reinterpret_cast<Cplx<float> *>(state), N, c0, J);
-    else
-        hipLaunchKernelGGL(k_involution<double>, dim3(blocks_for(N)), dim3(NT), 0, st,
-                           reinterpret_cast<Cplx<double> *>(state), N, c0, J);
+    // a pair is whole lines apart only when no moved position is below the line
+    if (dt == QS_C64) {
+        auto *s = reinterpret_cast<Cplx<float> *>(state);
+        if (c0 >= line_bits<float>())
+            hipLaunchKernelGGL((k_involution<float, true>), dim3(blocks_for(N)), dim3(NT), 0, st, s, N, c0, J);
+        else
+            hipLaunchKernelGGL((k_involution<float, false>), dim3(blocks_for(N)), dim3(NT), 0, st, s, N, c0, J);
+    } else {
+        auto *s = reinterpret_cast<Cplx<double> *>(state);
+        if (c0 >= line_bits<double>())
+            hipLaunchKernelGGL((k_involution<double, true>), dim3(blocks_for(N)), dim3(NT), 0, st, s, N, c0, J);
+        else
+            hipLaunchKernelGGL((k_involution<double, false>), dim3(blocks_for(N)), dim3(NT), 0, st, s, N, c0, J);
+    }
     check_launch("involution");
 }
 

@@ -89,7 +89,10 @@ struct TileArgs {
                                   // bit 1: the store layout is that of the last OP_REMAP, else
                                   // tile-local index j * NT + tid reached through LDS;
                                   // bit 2 (only with no ops): the amplitude at tile-local index
-                                  // t is stored at index sperm(t) (a bit permutation)
+                                  // t is stored at index sperm(t) (a bit permutation);
+                                  // bit 3: the lowest tile positions are the lowest
+                                  // physical positions, so every load and store moves
+                                  // whole 128-byte lines (non-temporal access pays)
     int32_t pad;
     uint8_t sperm[16];            // tile bit b moves to tile bit sperm[b] (io bit 2)
 };

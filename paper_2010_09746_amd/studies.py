@@ -4,8 +4,9 @@
   a one-qubit gate on every target qubit (the GPU counterpart of the paper's
   Fig. 1, which times one gate per qubit index on a distributed state), CNOT
   and CZ for low / high qubit pairs, the position-exchange data movement for
-  1..8 exchanged pairs (PermuteQubits, Section 2 and Appendix A), and the
-  read-out of every <Z_q>.
+  1..8 exchanged pairs (PermuteQubits, Section 2 and Appendix A), the
+  fused tile pass against the number of gates it carries (HBM-bound with few
+  gates, ALU-bound with many), and the read-out of every <Z_q>.
 * ``qft_study``: the quantum Fourier transform and the QFT-like circuit of
   Appendix C through the permutation pass; the QFT output is checked against
   its closed form at sampled indices.
@@ -24,8 +25,8 @@ import torch
 
 from . import qsim as Q
 
-from workloads import (H, KIND_CX, KIND_CZ, KIND_U, make_gates, paper_random_circuit, qft_circuit,
-                       qft_like_circuit, sample_indices)
+from workloads import (H, KIND_CX, KIND_CZ, KIND_U, MASTER_SEED, haar_u2, make_gates, paper_random_circuit,
+                       qft_circuit, qft_like_circuit, sample_indices)
 
 
 def _profiled(fn):
@@ -81,6 +82,19 @@ def kernel_sweep(n: int = 30, dtype: str = "c128", reps: int = 3) -> dict:
         p = _profiled(go)["move_involution"]
         moves.append(dict(pairs=npairs, moved_fraction=1.0 - 2.0 ** -npairs, avg_ms=p["avg_ms"], gbs=p["gbs"]))
     res["permute"] = moves
+    # one fused tile pass carrying G Haar one-qubit gates on the tile's qubits
+    rng = np.random.default_rng(MASTER_SEED + 17)
+    k = min(12, n)
+    fused = []
+    for ng in (1, 2, 4, 8, 12, 16, 24, 32, 48):
+        g = make_gates([(KIND_U, i % k, -1, haar_u2(rng)) for i in range(ng)])
+        prog = Q.Program(g, n, dtype, form="pass", k_tile=k, max_swaps=16, pinned=3, perm_exec="relabel")
+        st.run_program(prog)
+        p = _profiled(lambda: [st.run_program(prog) for _ in range(reps)])["tile_pass"]
+        prog.close()
+        fused.append(dict(gates=ng, avg_ms=p["avg_ms"], gbs=p["gbs"],
+                          tflops=14.0 * ng * float(1 << n) / (p["avg_ms"] * 1e-3) / 1e12))
+    res["tile_pass_by_gates"] = fused
     st.expect_z()
     p = _profiled(lambda: [st.expect_z() for _ in range(reps)])
     res["zsum"] = p.get("zsum")
