@@ -180,14 +180,16 @@ public:
     // Number of not-scheduled gates that become schedulable under sigma;
     // optionally collects the non-diagonal targets (qubits) of gates that are
     // reached (all predecessors done or counted) but are not local.
+    // The closure does not depend on the order gates are visited in, so a
+    // plain work list replaces the program-order heap of sweep().
     int64_t closure(const int *sigma, std::vector<char> *reach_targets)
     {
-        MinHeap h(std::greater<int>(), frontier_);
+        work_.assign(frontier_.begin(), frontier_.end());
         touched_.clear();
         int64_t cnt = 0;
-        while (!h.empty()) {
-            int v = h.top();
-            h.pop();
+        while (!work_.empty()) {
+            const int v = work_.back();
+            work_.pop_back();
             if (!is_local(gi_[v], sigma, m_)) {
                 if (reach_targets)
                     (*reach_targets)[gi_[v].target] = 1;
@@ -200,7 +202,7 @@ public:
                     touched_.push_back(s);
                 }
                 if (--tmp_[s] == 0)
-                    h.push(s);
+                    work_.push_back(s);
             }
         }
         for (int s : touched_)
@@ -237,7 +239,7 @@ private:
     const std::vector<GateInfo> &gi_;
     const Dag &d_;
     int n_, m_;
-    std::vector<int> npend_, tmp_, touched_;
+    std::vector<int> npend_, tmp_, touched_, work_;
     std::vector<char> done_;
     std::vector<int> frontier_;
     int64_t remaining_;
