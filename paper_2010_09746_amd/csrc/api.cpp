@@ -30,6 +30,9 @@ struct qs_state {
     uint64_t *d_idx = nullptr;     // gather indices
     double *d_amp = nullptr;       // gathered amplitudes
     int64_t idx_cap = 0;
+    qsim::TileOp *d_ops = nullptr; // operation tables of qs_run_circuit (device)
+    qsim::TileOp *h_ops = nullptr; // their pinned host staging
+    size_t ops_cap = 0;
 };
 
 namespace qsim {
@@ -359,14 +362,11 @@ void upload_ops(Program &p)
     p.dev = dev;
 }
 
-void run_launches(qs_state *s, Program &p)
+// Enqueue launches [a, b) of p; tile operations are read from d_ops.
+void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, const TileOp *d_ops)
 {
-    need(s->n == p.n, "program compiled for a different qubit count");
-    need(s->dt == p.dt, "program compiled for a different amplitude type");
-    if (s->sigma != p.sigma0)
-        fail(QS_ERR_STATE, "state placement differs from the program's starting placement");
-    upload_ops(p);
-    for (const Launch &L : p.launches) {
+    for (size_t li = a_idx; li < b_idx; ++li) {
+        const Launch &L = p.launches[li];
         switch (L.type) {
         case L_PLAIN:
             timed(s->stream, gate_class(L.gate.kind), gate_bytes(L.gate.kind, s->n, elem_bytes(s->dt)),
@@ -379,7 +379,7 @@ void run_launches(qs_state *s, Program &p)
             TileArgs a{};
             tile_args_from_launch(L, a);
             a.state = s->buf;
-            a.ops = p.d_ops + L.op_begin;
+            a.ops = d_ops + L.op_begin;
             a.n_hi = s->n - L.k;
             const uint64_t tiles = 1ull << (s->n - L.k);
             timed(s->stream, P_TILE, 2.0 * (double)s->bytes, [&] {
@@ -392,7 +392,36 @@ void run_launches(qs_state *s, Program &p)
         }
         }
     }
+}
+
+void run_launches(qs_state *s, Program &p)
+{
+    need(s->n == p.n, "program compiled for a different qubit count");
+    need(s->dt == p.dt, "program compiled for a different amplitude type");
+    if (s->sigma != p.sigma0)
+        fail(QS_ERR_STATE, "state placement differs from the program's starting placement");
+    upload_ops(p);
+    launch_range(s, p, 0, p.launches.size(), p.d_ops);
     s->sigma = p.sigma_final;
+}
+
+// Operation tables of qs_run_circuit: a device buffer and its pinned staging,
+// kept with the state and grown on demand (every call ends synchronised, so
+// the next one may overwrite them).
+void ensure_op_buffers(qs_state *s, size_t n_ops)
+{
+    if (n_ops <= s->ops_cap)
+        return;
+    if (s->d_ops)
+        (void)hipFree(s->d_ops);
+    if (s->h_ops)
+        (void)hipHostFree(s->h_ops);
+    s->d_ops = nullptr;
+    s->h_ops = nullptr;
+    s->ops_cap = 0;
+    hipchk(hipMalloc(&s->d_ops, n_ops * sizeof(TileOp)), "hipMalloc(tile ops)");
+    hipchk(hipHostMalloc(&s->h_ops, n_ops * sizeof(TileOp), hipHostMallocDefault), "hipHostMalloc(tile ops)");
+    s->ops_cap = n_ops;
 }
 
 qs_run_opts default_opts()
@@ -485,6 +514,10 @@ qs_status qs_state_destroy(qs_state *s)
             (void)hipFree(s->d_idx);
         if (s->d_amp)
             (void)hipFree(s->d_amp);
+        if (s->d_ops)
+            (void)hipFree(s->d_ops);
+        if (s->h_ops)
+            (void)hipHostFree(s->h_ops);
         delete s;
     });
 }
@@ -702,20 +735,51 @@ qs_status qs_run_program(qs_state *s, const qs_program *p)
     });
 }
 
+// Compile and run.  In the pass form the launches of each segment are
+// enqueued as soon as the pass has fixed it, so the device works on the first
+// segments while the host is still choosing later permutations.
 qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts)
 {
-    qs_program *p = nullptr;
-    qs_status rc = QS_OK;
-    rc = qs_compile(gates, n_gates, s ? s->n : 0, s ? s->dt : QS_C128, s ? s->sigma.data() : nullptr, opts, &p);
-    if (rc != QS_OK)
-        return rc;
-    rc = qs_run_program(s, p);
-    std::string err = g_err;
-    // the program's device tables must outlive the enqueued work
-    (void)hipStreamSynchronize(s->stream);
-    qs_program_destroy(p);
-    g_err = err;
-    return rc;
+    return guard([&] {
+        need(s != nullptr, "state is NULL");
+        need(n_gates >= 0 && (n_gates == 0 || gates != nullptr), "bad arguments");
+        const qs_run_opts o = opts ? *opts : default_opts();
+        Program p;
+        // every gate gives at most one operation and one re-layout, plus one
+        // re-layout per segment
+        const size_t bound = 3 * (size_t)n_gates + 16;
+        if (o.form == QS_FORM_PASS)
+            ensure_op_buffers(s, bound);
+        size_t launched = 0, uploaded = 0;
+        auto progress = [&](Program &pp) {
+            if (pp.ops.size() > bound)
+                fail(QS_ERR_UNSUPPORTED, "internal: operation table larger than its bound");
+            if (pp.ops.size() > uploaded) {
+                const size_t cnt = pp.ops.size() - uploaded;
+                std::memcpy(s->h_ops + uploaded, pp.ops.data() + uploaded, cnt * sizeof(TileOp));
+                hipchk(hipMemcpyAsync(s->d_ops + uploaded, s->h_ops + uploaded, cnt * sizeof(TileOp),
+                                      hipMemcpyHostToDevice, s->stream),
+                       "hipMemcpyAsync(tile ops)");
+                uploaded = pp.ops.size();
+            }
+            launch_range(s, pp, launched, pp.launches.size(), s->d_ops);
+            launched = pp.launches.size();
+        };
+        if (o.form == QS_FORM_PASS) {
+            compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p, progress);
+            s->sigma = p.sigma_final;
+        } else {
+            compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p);
+            run_launches(s, p);
+        }
+        // the tables (and the staging the copies read) are reused next call;
+        // a program-owned table is freed with p
+        hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        if (p.d_ops) {
+            (void)hipFree(p.d_ops);
+            p.d_ops = nullptr;
+        }
+    });
 }
 
 qs_status qs_synchronize(qs_state *s)

@@ -104,10 +104,6 @@ bool gates_commute(const qs_gate &a, const GateInfo &ia, const qs_gate &b, const
 
 namespace {
 
-struct Dag {
-    std::vector<std::vector<int>> pred, succ;
-};
-
 Dag build_dag(const qs_gate *g, const std::vector<GateInfo> &gi, int n)
 {
     const int ng = (int)gi.size();
@@ -142,6 +138,8 @@ inline bool is_local(const GateInfo &gi, const int *sigma, int m)
 }
 
 using MinHeap = std::priority_queue<int, std::vector<int>, std::greater<int>>;
+
+}  // namespace
 
 class PassState {
 public:
@@ -245,74 +243,88 @@ private:
     int64_t remaining_;
 };
 
-}  // namespace
+
+// One iteration at a time: apply every ready local gate, then insert one
+// PermuteQubits (or, when no exchange helps, run one gate as global).
+PassRunner::PassRunner(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned, const std::vector<int> &sigma0)
+    : n_(n), m_(m), r_(r), pinned_(pinned), gi_(ng), sigma_(sigma0)
+{
+    for (int64_t v = 0; v < ng; ++v)
+        gi_[v] = analyse(g[v]);
+    dag_ = build_dag(g, gi_, n);
+    ps_ = new PassState(gi_, dag_, n, m);
+}
+
+PassRunner::~PassRunner() { delete ps_; }
+
+bool PassRunner::step(std::vector<Instr> &out)
+{
+    PassState &ps = *ps_;
+    if (ps.remaining() == 0)
+        return false;
+    const int n = n_, m = m_;
+    emitted_.clear();
+    ps.sweep(sigma_.data(), emitted_);
+    for (int v : emitted_)
+        out.push_back(Instr{0, v, {}});
+    stats_.n_apply += (int64_t)emitted_.size();
+    if (ps.remaining() == 0)
+        return false;
+
+    std::vector<int> cur = sigma_, cand(n), best(n);
+    std::vector<char> targets(n);
+    int64_t base = 0;
+    int swaps = 0;
+    for (int step = 0; step < r_; ++step) {
+        std::fill(targets.begin(), targets.end(), 0);
+        ps.closure(cur.data(), &targets);
+        int64_t best_a = base;
+        bool found = false;
+        for (int l = 0; l < n; ++l) {
+            if (!(cur[l] < m && cur[l] >= pinned_))
+                continue;
+            for (int gq = 0; gq < n; ++gq) {
+                if (cur[gq] < m || !targets[gq])
+                    continue;
+                cand = cur;
+                cand[l] = cur[gq];
+                cand[gq] = cur[l];
+                int64_t a = ps.closure(cand.data(), nullptr);
+                if (a > best_a) {
+                    best_a = a;
+                    best = cand;
+                    found = true;
+                }
+            }
+        }
+        if (!found)
+            break;
+        cur = best;
+        base = best_a;
+        ++swaps;
+    }
+    if (swaps > 0) {
+        sigma_ = cur;
+        out.push_back(Instr{1, -1, sigma_});
+        ++stats_.n_perm;
+        stats_.n_swaps += swaps;
+    } else {
+        int v = ps.take_first_ready();
+        out.push_back(Instr{2, v, {}});
+        ++stats_.n_global;
+    }
+    return true;
+}
 
 std::vector<Instr> run_pass(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned,
                             const std::vector<int> &sigma0, PassStats *st)
 {
-    std::vector<GateInfo> gi(ng);
-    for (int64_t v = 0; v < ng; ++v)
-        gi[v] = analyse(g[v]);
-    Dag d = build_dag(g, gi, n);
-    PassState ps(gi, d, n, m);
-    std::vector<int> sigma = sigma0, cur(n), cand(n), best(n);
+    PassRunner pr(g, ng, n, m, r, pinned, sigma0);
     std::vector<Instr> out;
-    std::vector<int> emitted;
-    std::vector<char> targets(n);
-    PassStats s{};
-    while (ps.remaining() > 0) {
-        emitted.clear();
-        ps.sweep(sigma.data(), emitted);
-        for (int v : emitted)
-            out.push_back(Instr{0, v, {}});
-        s.n_apply += (int64_t)emitted.size();
-        if (ps.remaining() == 0)
-            break;
-
-        cur = sigma;
-        int64_t base = 0;
-        int swaps = 0;
-        for (int step = 0; step < r; ++step) {
-            std::fill(targets.begin(), targets.end(), 0);
-            ps.closure(cur.data(), &targets);
-            int64_t best_a = base;
-            bool found = false;
-            for (int l = 0; l < n; ++l) {
-                if (!(cur[l] < m && cur[l] >= pinned))
-                    continue;
-                for (int gq = 0; gq < n; ++gq) {
-                    if (cur[gq] < m || !targets[gq])
-                        continue;
-                    cand = cur;
-                    cand[l] = cur[gq];
-                    cand[gq] = cur[l];
-                    int64_t a = ps.closure(cand.data(), nullptr);
-                    if (a > best_a) {
-                        best_a = a;
-                        best = cand;
-                        found = true;
-                    }
-                }
-            }
-            if (!found)
-                break;
-            cur = best;
-            base = best_a;
-            ++swaps;
-        }
-        if (swaps > 0) {
-            sigma = cur;
-            out.push_back(Instr{1, -1, sigma});
-            ++s.n_perm;
-            s.n_swaps += swaps;
-        } else {
-            int v = ps.take_first_ready();
-            out.push_back(Instr{2, v, {}});
-            ++s.n_global;
-        }
+    while (pr.step(out)) {
     }
     if (st)
-        *st = s;
+        *st = pr.stats();
     return out;
 }
 
@@ -640,7 +652,7 @@ void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a)
 }
 
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0_in,
-                     const qs_run_opts &o, Program &p)
+                     const qs_run_opts &o, Program &p, const std::function<void(Program &)> &progress)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (n < 1 || n > MAX_COMPILE_QUBITS)
@@ -701,13 +713,6 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
             fail(QS_ERR_ARG, "pinned must be in [0, k_tile]");
         if (o.perm_exec != QS_PERM_MOVE && o.perm_exec != QS_PERM_RELABEL)
             fail(QS_ERR_ARG, "unknown perm_exec");
-        PassStats ps;
-        p.instrs = run_pass(g, ng, n, k, o.max_swaps, o.pinned, p.sigma0, &ps);
-        p.stats.n_apply = ps.n_apply;
-        p.stats.n_perm = ps.n_perm;
-        p.stats.n_global = ps.n_global;
-        p.stats.n_swaps = ps.n_swaps;
-
         // tile passes need 7 <= k and a tile that fits in one CU's LDS; a larger
         // local set (e.g. a pass planned for several devices) runs its
         // segments gate by gate
@@ -717,72 +722,94 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
             tile_shape(k, dt, o.reg_bits > 0 ? o.reg_bits : pass_reg_bits(k, dt), &log_r, &log_nt);
         std::vector<int> spass = p.sigma0;
         size_t i = 0;
-        while (i < p.instrs.size()) {
-            const Instr &I = p.instrs[i];
-            if (I.type == 1) {
-                spass = I.sigma;
-                if (o.perm_exec == QS_PERM_MOVE) {
+        // Lower the instructions from i on.  A run of ApplyGate instructions is
+        // a complete segment once an instruction of another kind follows it
+        // (or, with final, at the end).
+        auto lower = [&](bool final) {
+            while (i < p.instrs.size()) {
+                const Instr &I = p.instrs[i];
+                if (I.type == 1) {
+                    spass = I.sigma;
+                    if (o.perm_exec == QS_PERM_MOVE) {
+                        Launch L;
+                        L.type = L_MOVE;
+                        L.pi.resize(n);
+                        for (int q = 0; q < n; ++q)
+                            L.pi[sphys[q]] = spass[q];
+                        p.launches.push_back(L);
+                        ++p.stats.n_move_passes;
+                        sphys = spass;
+                    }
+                    ++i;
+                    continue;
+                }
+                if (I.type == 2) {
+                    plain(I.gate);
+                    ++i;
+                    continue;
+                }
+                // a run of local ApplyGate instructions = one segment
+                size_t j = i;
+                while (j < p.instrs.size() && p.instrs[j].type == 0)
+                    ++j;
+                if (j == p.instrs.size() && !final)
+                    return;
+                if (!tiled) {
+                    for (size_t t = i; t < j; ++t)
+                        plain(p.instrs[t].gate);
+                    i = j;
+                    continue;
+                }
+                // tile positions: physical positions of the k local qubits
+                std::vector<int> pos;
+                for (int q = 0; q < n; ++q)
+                    if (spass[q] < k)
+                        pos.push_back(sphys[q]);
+                std::sort(pos.begin(), pos.end());
+                std::vector<int> tbit(n, -1);
+                for (int b = 0; b < k; ++b)
+                    tbit[pos[b]] = b;
+                const size_t chunk = o.max_fuse > 0 ? (size_t)o.max_fuse : (j - i);
+                for (size_t c0 = i; c0 < j; c0 += chunk) {
+                    size_t c1 = std::min(j, c0 + chunk);
+                    std::vector<LGate> lg;
+                    for (size_t t = c0; t < c1; ++t) {
+                        int v = p.instrs[t].gate;
+                        LGate L = lower_gate(g[v], gi[v], sphys, tbit);
+                        L.src = v;
+                        lg.push_back(L);
+                    }
                     Launch L;
-                    L.type = L_MOVE;
-                    L.pi.resize(n);
-                    for (int q = 0; q < n; ++q)
-                        L.pi[sphys[q]] = spass[q];
+                    L.type = L_TILE;
+                    L.k = k;
+                    L.log_r = log_r;
+                    L.log_nt = log_nt;
+                    L.pos = pos;
+                    L.op_begin = (int)p.ops.size();
+                    p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops);
+                    L.op_count = (int)p.ops.size() - L.op_begin;
+                    set_direct_io(L, p.ops, dt);
                     p.launches.push_back(L);
-                    ++p.stats.n_move_passes;
-                    sphys = spass;
+                    ++p.stats.n_tile_passes;
                 }
-                ++i;
-                continue;
-            }
-            if (I.type == 2) {
-                plain(I.gate);
-                ++i;
-                continue;
-            }
-            // a run of local ApplyGate instructions = one segment
-            size_t j = i;
-            while (j < p.instrs.size() && p.instrs[j].type == 0)
-                ++j;
-            if (!tiled) {
-                for (size_t t = i; t < j; ++t)
-                    plain(p.instrs[t].gate);
                 i = j;
-                continue;
             }
-            // tile positions: physical positions of the k local qubits
-            std::vector<int> pos;
-            for (int q = 0; q < n; ++q)
-                if (spass[q] < k)
-                    pos.push_back(sphys[q]);
-            std::sort(pos.begin(), pos.end());
-            std::vector<int> tbit(n, -1);
-            for (int b = 0; b < k; ++b)
-                tbit[pos[b]] = b;
-            const size_t chunk = o.max_fuse > 0 ? (size_t)o.max_fuse : (j - i);
-            for (size_t c0 = i; c0 < j; c0 += chunk) {
-                size_t c1 = std::min(j, c0 + chunk);
-                std::vector<LGate> lg;
-                for (size_t t = c0; t < c1; ++t) {
-                    int v = p.instrs[t].gate;
-                    LGate L = lower_gate(g[v], gi[v], sphys, tbit);
-                    L.src = v;
-                    lg.push_back(L);
-                }
-                Launch L;
-                L.type = L_TILE;
-                L.k = k;
-                L.log_r = log_r;
-                L.log_nt = log_nt;
-                L.pos = pos;
-                L.op_begin = (int)p.ops.size();
-                p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops);
-                L.op_count = (int)p.ops.size() - L.op_begin;
-                set_direct_io(L, p.ops, dt);
-                p.launches.push_back(L);
-                ++p.stats.n_tile_passes;
-            }
-            i = j;
+        };
+        // the pass and the lowering advance together, so a caller can start
+        // the first launches while later permutations are still being chosen
+        PassRunner pr(g, ng, n, k, o.max_swaps, o.pinned, p.sigma0);
+        bool more = true;
+        while (more) {
+            more = pr.step(p.instrs);
+            lower(!more);
+            if (progress)
+                progress(p);
         }
+        const PassStats &ps = pr.stats();
+        p.stats.n_apply = ps.n_apply;
+        p.stats.n_perm = ps.n_perm;
+        p.stats.n_global = ps.n_global;
+        p.stats.n_swaps = ps.n_swaps;
         p.sigma_final = sphys;
     } else {
         fail(QS_ERR_ARG, "unknown form");

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -158,6 +159,32 @@ struct PassStats {
 std::vector<Instr> run_pass(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned,
                             const std::vector<int> &sigma0, PassStats *st);
 
+class PassState;
+struct Dag {
+    std::vector<std::vector<int>> pred, succ;
+};
+// The same pass, one iteration per step(): the instructions of the sweep and
+// the PermuteQubits (or global gate) that follows it are appended to out;
+// false once every gate is scheduled.
+class PassRunner {
+public:
+    PassRunner(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned, const std::vector<int> &sigma0);
+    ~PassRunner();
+    PassRunner(const PassRunner &) = delete;
+    PassRunner &operator=(const PassRunner &) = delete;
+    bool step(std::vector<Instr> &out);
+    const PassStats &stats() const { return stats_; }
+    const std::vector<GateInfo> &gate_info() const { return gi_; }
+
+private:
+    int n_, m_, r_, pinned_;
+    std::vector<GateInfo> gi_;
+    Dag dag_;
+    PassState *ps_ = nullptr;
+    std::vector<int> sigma_, emitted_;
+    PassStats stats_;
+};
+
 struct Program {
     int n = 0;
     qs_dtype dt = QS_C128;
@@ -172,8 +199,11 @@ struct Program {
     TileOp *d_ops = nullptr;
 };
 
+// Compile a circuit.  With progress, the pass form calls it after each pass
+// iteration, once the launches of every completed segment are in p.launches
+// (and their operations in p.ops); launches already there never change.
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0,
-                     const qs_run_opts &o, Program &p);
+                     const qs_run_opts &o, Program &p, const std::function<void(Program &)> &progress = {});
 
 }  // namespace qsim
 
