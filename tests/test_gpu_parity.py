@@ -234,6 +234,26 @@ def test_program_reuse_and_placement_check():
     _check(st, O.run(g, n), "c128")
 
 
+@pytest.mark.parametrize("dt,perm_exec", [("c128", "relabel"), ("c64", "relabel"), ("c128", "move")])
+def test_streamed_run_equals_compiled_program(dt, perm_exec):
+    """qs_run_circuit enqueues each segment while the pass continues; the
+    result and the final placement are those of the program compiled whole
+    (same kernels in the same order: bit-identical)."""
+    n = 16
+    _say(f"streamed run vs program {dt} {perm_exec}")
+    g = layered_circuit(n, 12, seed=17)
+    opts = dict(form="pass", k_tile=9, max_swaps=4, pinned=3 if perm_exec == "relabel" else 0, perm_exec=perm_exec)
+    a = Q.State(n, dt)
+    a.run(g, **opts)
+    b = Q.State(n, dt)
+    P = Q.Program(g, n, dt, **opts)
+    assert P.stats()["n_perm"] > 0
+    b.run_program(P)
+    assert a.sigma == b.sigma
+    assert np.array_equal(a.to_numpy(), b.to_numpy())
+    _check(a, O.run(g, n), dt)
+
+
 def test_empty_circuit_and_identity_permutation():
     n = 9
     st = Q.State(n, "c64")
