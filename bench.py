@@ -122,7 +122,7 @@ def precision(a):
     upd = len(gates) * float(1 << n)
     out = {}
     states = {}
-    for dt, k in (("c64", a.k + 1), ("c128", a.k)):
+    for dt, k in (("c64", a.k), ("c128", a.k)):
         st = Q.State(n, dt)
         opts = dict(form="pass", k_tile=k, max_swaps=a.r, perm_exec="relabel", pinned=a.pinned)
         st.run(gates, **opts)  # warm-up

@@ -766,7 +766,15 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, con
             launched = pp.launches.size();
         };
         if (o.form == QS_FORM_PASS) {
-            compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p, progress);
+            try {
+                compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p, progress);
+            } catch (...) {
+                // launches already enqueued read the op tables: let them
+                // finish before the error is reported (the state then holds a
+                // partly applied circuit)
+                (void)hipStreamSynchronize(s->stream);
+                throw;
+            }
             s->sigma = p.sigma_final;
         } else {
             compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p);
