@@ -214,7 +214,13 @@ qs_status qs_program_instructions(const qs_program *p, int32_t *buf, int64_t cap
 /* Enqueue a compiled program on the state's stream.  The state's placement
  * must equal the program's sigma0; afterwards it is the program's final one. */
 qs_status qs_run_program(qs_state *s, const qs_program *p);
-/* Compile with the state's placement, run, destroy the program. */
+/* Compile with the state's placement and run (Section 3).  In the pass form
+ * each segment is enqueued as soon as the pass has fixed the permutation that
+ * follows it, so the device starts while the host is still compiling.  Returns
+ * after the state's stream is synchronised.  Gates are checked before any
+ * launch; an error after launches were enqueued (a HIP failure) leaves the
+ * state with a partly applied circuit.  opts NULL: the pass form, k_tile 12,
+ * r = 1, moved placements. */
 qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates,
                          const qs_run_opts *opts);
 
