@@ -343,8 +343,7 @@ int pass_reg_bits(int k, qs_dtype dt)
 
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt)
 {
-    // measured on MI355X: 8 complex128 or 16 complex64 amplitudes per thread
-    int lr = reg_bits_opt > 0 ? reg_bits_opt : (dt == QS_C128 ? 3 : 4);
+    int lr = reg_bits_opt > 0 ? reg_bits_opt : pass_reg_bits(k, dt);
     lr = std::min(lr, 5);
     lr = std::max(lr, k - 10);   // at most 1024 threads
     lr = std::min(lr, k - 6);    // at least one wavefront
@@ -719,7 +718,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         const bool tiled = k >= MIN_TILE_BITS && (size_t(dt == QS_C64 ? 8 : 16) << k) <= MAX_TILE_BYTES;
         int log_r = 0, log_nt = 0;
         if (tiled)
-            tile_shape(k, dt, o.reg_bits > 0 ? o.reg_bits : pass_reg_bits(k, dt), &log_r, &log_nt);
+            tile_shape(k, dt, o.reg_bits, &log_r, &log_nt);
         std::vector<int> spass = p.sigma0;
         size_t i = 0;
         // Lower the instructions from i on.  A run of ApplyGate instructions is

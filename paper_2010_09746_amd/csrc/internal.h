@@ -223,8 +223,10 @@ void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a);
 void tile_args_for_positions(const std::vector<int> &pos, int log_nt, int log_r, TileArgs &a);
 
 // choose register bits / threads for a tile of k bits
+// Tile shape: 2^log_r amplitudes per thread (reg_bits_opt, or pass_reg_bits
+// when 0), clamped to 64..1024 threads.
 void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);
-// register bits of a tile pass of the permutation form when none are asked for
+// register bits of a tile when none are asked for (measured)
 int pass_reg_bits(int k, qs_dtype dt);
 
 // ---------------------------------------------------------------------------

@@ -89,3 +89,21 @@ def test_realtime_trace_latencies():
         ref = O.run(r["gates"], r["n"])
         assert np.abs(res[r["id"]]["z"] - O.expect_z(ref, r["n"])).max() <= 1e-5
     srv.close()
+
+
+@pytest.mark.parametrize("dt,k", [("c128", 11), ("c64", 12)])
+def test_default_register_shape_at_large_tiles(dt, k):
+    """With reg_bits = 0 the server and the compiled programs take the same
+    register shape (16 amplitudes per thread here); results match the oracle."""
+    _say(f"serving: default shape {dt} k={k}")
+    reqs = _requests(6, k, k + 3, 3, 8, seed=11)
+    srv = Server(dt, k_tile=k, max_swaps=8, pinned=3, max_slots=16)
+    res, _ = srv.serve(reqs, realtime=False)
+    tol = 1e-10 if dt == "c128" else 1e-5
+    for r in reqs:
+        n, g = r["n"], r["gates"]
+        ref = O.run(g, n)
+        mix = res[r["id"]]
+        assert np.abs(mix["z"] - O.expect_z(ref, n)).max() <= tol
+        assert np.abs(mix["amps"] - ref[np.asarray(r["samples"], dtype=np.int64)]).max() <= tol
+    srv.close()
