@@ -77,7 +77,7 @@ def kernel_source_hash():
     import hashlib
 
     h = hashlib.sha1()
-    for f in ("tile_kernel.cuh", "common.cuh", "internal.h"):
+    for f in ("tile_kernel.cuh", "common.cuh", "tile_args.h"):
         with open(os.path.join(ROOT, "paper_2010_09746_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "qsim.h"
+#include "tile_args.h"
 
 namespace qsim {
 
@@ -30,40 +31,6 @@ int matrix_action(const double *u);
 GateInfo analyse(const qs_gate &g);
 bool gates_commute(const qs_gate &a, const GateInfo &ia, const qs_gate &b, const GateInfo &ib);
 
-// ---------------------------------------------------------------------------
-// tile kernel operations
-
-enum TileOpKind : int32_t {
-    OP_U = 0,      // dense 2x2 on register slot `slot`
-    OP_X = 1,      // exchange the pair on register slot `slot`
-    OP_DIAG = 2,   // multiply by d0 (m[0..1]) / d1 (m[2..3]) selected by the target bit
-    OP_NEG = 3,    // negate where every control bit is 1
-    OP_REMAP = 4,  // move amplitudes through LDS to a new register layout
-};
-
-// One operation of a fused tile pass (104 bytes, every field at least 32 bits
-// wide and naturally aligned so that the kernel reads it with scalar loads).  Its controls are split by
-// where the control bit lives under the register layout in force when the
-// operation runs: register slots (rmask, a mask over slots), thread bits
-// (lmask, a mask over tile-local index bits) and positions outside the tile
-// (hmask, a mask over physical positions).  The operation acts where every
-// control bit is 1.
-struct TileOp {
-    int32_t kind;
-    int32_t slot;      // OP_U/OP_X: target register slot.  OP_DIAG: target
-                       // register slot, or -1 (target is the thread bit tlane)
-                       // or -2 (target outside the tile, at hbit)
-    uint32_t rmask;    // OP_REMAP: register tile bits, 4 bits each (slot s at bits 4s..4s+3)
-    uint32_t lmask;
-    uint32_t tlane;
-    uint32_t pad;
-    uint64_t hmask;
-    uint64_t hbit;     // OP_DIAG target outside the tile; OP_REMAP: the tile bit of each
-                       // thread-id bit, 4 bits each (thread bit i at bits 4i..4i+3)
-    double m[8];
-};
-static_assert(sizeof(TileOp) == 104, "TileOp layout");
-
 constexpr int MAX_TILE_BITS = 15;
 constexpr int MIN_TILE_BITS = 7;
 constexpr int MAX_QUBITS = 34;          // states
@@ -72,32 +39,6 @@ constexpr size_t MAX_TILE_BYTES = 262144;   // one tile of a pass (LDS holds hal
 constexpr size_t MAX_BATCH_TILE_BYTES = 131072;  // one tile of the batching and serving forms
 constexpr int DIRECT_RUN_BYTES = 128;       // contiguous bytes a direct tile load or store keeps together
 
-// Kernel arguments of one tile pass, passed by value.  The load and store
-// layouts give, for each thread-id bit and each register-slot bit, the
-// physical position it addresses.
-struct TileArgs {
-    void *state;
-    const TileOp *ops;
-    int32_t n_ops;
-    int32_t n_hi;                 // positions outside the tile
-    uint8_t pos[16];              // tile bit b -> physical position (ascending)
-    uint8_t ld_lane[16];          // load layout: thread-id bit -> position
-    uint8_t ld_reg[8];            // load layout: slot bit -> position
-    uint8_t st_lane[16];          // store layout: thread-id bit -> position
-    uint8_t st_reg[8];            // store layout: slot bit -> position
-    uint32_t io;                  // bit 0: the load layout is that of ops[0] (an OP_REMAP, then
-                                  // skipped), else tile-local index j * NT + tid;
-                                  // bit 1: the store layout is that of the last OP_REMAP, else
-                                  // tile-local index j * NT + tid reached through LDS;
-                                  // bit 2 (only with no ops): the amplitude at tile-local index
-                                  // t is stored at index sperm(t) (a bit permutation);
-                                  // bit 3: the lowest tile positions are the lowest
-                                  // physical positions, so every load and store moves
-                                  // whole 128-byte lines (non-temporal access pays)
-    int32_t pad;
-    uint8_t sperm[16];            // tile bit b moves to tile bit sperm[b] (io bit 2)
-};
-static_assert(sizeof(TileArgs) == 112, "TileArgs layout");
 
 // ---------------------------------------------------------------------------
 // batching form: one persistent launch over many circuits
