@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = the OpenMP default)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "tile_pass_traffic.json"))
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many GiB 3 times (a plain copy kernel of "
@@ -83,14 +84,17 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(gates, n, seconds):
+def cpu_baseline(gates, n, seconds, threads=0):
     """The oracle (plain C, complex128, OpenMP) on this host: gates of the
-    same circuit applied one by one until ``seconds`` have elapsed."""
+    same circuit applied one by one until ``seconds`` have elapsed, with
+    ``threads`` OpenMP threads (0: the OpenMP default)."""
     import numpy as np
 
     import oracle as O
 
     O.lib()
+    if threads > 0:
+        O.set_threads(threads)
     s = O.zero_state(n)
     done = 0
     t0 = time.perf_counter()
@@ -454,7 +458,7 @@ def main():
         st.close()
         del st
         torch.cuda.empty_cache()
-        cpu = cpu_baseline(gates, n, a.cpu_seconds)
+        cpu = cpu_baseline(gates, n, a.cpu_seconds, a.cpu_threads)
 
     value = amp_updates / ms_pass
     line = {

@@ -71,6 +71,8 @@ def lib():
         L.orc_commute.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_commute.restype = ctypes.c_int
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -117,6 +119,11 @@ def run(gates: np.ndarray, n: int, x: int = 0, state: np.ndarray | None = None) 
 def threads() -> int:
     """OpenMP threads used by the simulator loops."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the simulator loops with n threads."""
+    lib().orc_set_threads(int(n))
 
 
 def norm(state: np.ndarray, n: int) -> float:

@@ -182,3 +182,10 @@ int orc_threads(void)
 {
     return omp_get_max_threads();
 }
+
+/* Run the loops above with n threads (n >= 1). */
+void orc_set_threads(int n)
+{
+    if (n >= 1)
+        omp_set_num_threads(n);
+}
