@@ -434,6 +434,8 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 
 // Order the gates of one tile pass and insert register re-layouts.  The gates
 // may be reordered only along the commutation DAG restricted to the segment.
+constexpr int LOOKAHEAD_TARGETS = 8;
+
 int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::vector<GateInfo> &gi,
                      int k, int log_r, std::vector<TileOp> &ops)
 {
@@ -526,6 +528,49 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
         for (int v = 0; v < cnt; ++v)
             if (!emitted[v] && ready(v) && needs_reg(v))
                 add(lg[v].tb);
+        if ((int)want.size() > R) {
+            // more ready targets than register slots: of the first LOOK of
+            // them, keep the R that let the most gates run before the next
+            // re-layout (ties: program order)
+            const int LOOK = std::min((int)want.size(), LOOKAHEAD_TARGETS);
+            std::vector<int> best_set(want.begin(), want.begin() + R);
+            int best_run = -1;
+            std::vector<char> em(cnt);
+            for (uint32_t sel = 0; sel < (1u << LOOK); ++sel) {
+                if (__builtin_popcount(sel) != R)
+                    continue;
+                std::vector<int> set;
+                for (int b = 0; b < LOOK; ++b)
+                    if ((sel >> b) & 1u)
+                        set.push_back(want[b]);
+                std::copy(emitted.begin(), emitted.end(), em.begin());
+                int run = 0;
+                for (bool more = true; more;) {
+                    more = false;
+                    for (int v = 0; v < cnt; ++v) {
+                        if (em[v])
+                            continue;
+                        bool rd = true;
+                        for (int h : pred[v])
+                            rd &= em[h] != 0;
+                        if (!rd)
+                            continue;
+                        if (needs_reg(v) && std::find(set.begin(), set.end(), lg[v].tb) == set.end())
+                            continue;
+                        em[v] = 1;
+                        ++run;
+                        more = true;
+                    }
+                }
+                // subsets in increasing order of their lowest chosen index
+                // come later for equal counts, so only a larger count wins
+                if (run > best_run) {
+                    best_run = run;
+                    best_set = set;
+                }
+            }
+            want = best_set;
+        }
         for (int v = 0; v < cnt && (int)want.size() < R; ++v)
             if (!emitted[v] && needs_reg(v))
                 add(lg[v].tb);
