@@ -174,3 +174,17 @@ def test_cost_model_prediction_is_linear_in_counts():
     counts.update(tile_pass=2, u=10, remap=3, plain_cx=4, move_fraction=0.5)
     want = (2 * 1.0 + 10 * 2.0 + 3 * (1.0 + TILE_CLASSES.index("remap")) + 4 * 1.5 + 0.5 * 4.0) * 2 ** 4
     assert abs(cm.predict_counts(counts, 24, 10, 0) - want) < 1e-9
+
+
+def test_relayouts_bounded_on_layered_workload():
+    """Re-layouts of the 30-qubit layered workload (k = 12, 16 amplitudes per
+    thread): at least one per pass and one per 4 distinct targets of a layer,
+    at most one per gate; 172 with the look-ahead register choice."""
+    g = config_circuit(2)
+    P = Q.Program(g, 30, "c128", form="pass", k_tile=12, max_swaps=16, pinned=3, perm_exec="relabel", reg_bits=4)
+    c = P.op_counts()
+    st = P.stats()
+    P.close()
+    assert c["tile_pass"] == st["n_tile_passes"] == 43
+    assert 40 * 3 <= c["remap"] <= 172      # 12 local targets per layer, 4 register bits
+    assert c["remap"] == st["n_remaps"]
