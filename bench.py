@@ -267,7 +267,7 @@ def kernels(a):
     _study_line("one-qubit gate bandwidth (median over targets)", float(sorted(u)[len(u) // 2]), "GB/s",
                 sum(x["avg_ms"] for x in r["plain_u_per_target"]) / len(u),
                 {"workload": f"single kernels at n={a.n} {a.dtype}: one-qubit gate on each target, CX/CZ on "
-                             f"low/high pairs, position exchanges of 1..8 pairs, one fused tile pass (k=12) "
+                             f"low/high pairs, position exchanges of 1..8 pairs, one fused tile pass (k=12, 13) "
                              f"carrying 1..48 gates, <Z_q> read-out"}, r)
 
 

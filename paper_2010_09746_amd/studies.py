@@ -82,18 +82,19 @@ def kernel_sweep(n: int = 30, dtype: str = "c128", reps: int = 3) -> dict:
         p = _profiled(go)["move_involution"]
         moves.append(dict(pairs=npairs, moved_fraction=1.0 - 2.0 ** -npairs, avg_ms=p["avg_ms"], gbs=p["gbs"]))
     res["permute"] = moves
-    # one fused tile pass carrying G Haar one-qubit gates on the tile's qubits
+    # one fused tile pass carrying G Haar one-qubit gates on the tile's qubits,
+    # at tile sizes 2^12 and 2^13
     rng = np.random.default_rng(MASTER_SEED + 17)
-    k = min(12, n)
     fused = []
-    for ng in (1, 2, 4, 8, 12, 16, 24, 32, 48):
-        g = make_gates([(KIND_U, i % k, -1, haar_u2(rng)) for i in range(ng)])
-        prog = Q.Program(g, n, dtype, form="pass", k_tile=k, max_swaps=16, pinned=3, perm_exec="relabel")
-        st.run_program(prog)
-        p = _profiled(lambda: [st.run_program(prog) for _ in range(reps)])["tile_pass"]
-        prog.close()
-        fused.append(dict(gates=ng, avg_ms=p["avg_ms"], gbs=p["gbs"],
-                          tflops=14.0 * ng * float(1 << n) / (p["avg_ms"] * 1e-3) / 1e12))
+    for k in (min(12, n), min(13, n)):
+        for ng in (1, 2, 4, 8, 12, 16, 24, 32, 48):
+            g = make_gates([(KIND_U, i % k, -1, haar_u2(rng)) for i in range(ng)])
+            prog = Q.Program(g, n, dtype, form="pass", k_tile=k, max_swaps=16, pinned=3, perm_exec="relabel")
+            st.run_program(prog)
+            p = _profiled(lambda: [st.run_program(prog) for _ in range(reps)])["tile_pass"]
+            prog.close()
+            fused.append(dict(k=k, gates=ng, avg_ms=p["avg_ms"], gbs=p["gbs"],
+                              tflops=14.0 * ng * float(1 << n) / (p["avg_ms"] * 1e-3) / 1e12))
     res["tile_pass_by_gates"] = fused
     st.expect_z()
     p = _profiled(lambda: [st.expect_z() for _ in range(reps)])

@@ -89,7 +89,8 @@ def test_kernel_sweep_small():
     assert len(r["plain_u_per_target"]) == 20
     assert all(x["gbs"] > 0 for x in r["plain_u_per_target"])
     assert [m["pairs"] for m in r["permute"]] == list(range(1, 9))
-    assert [x["gates"] for x in r["tile_pass_by_gates"]] == [1, 2, 4, 8, 12, 16, 24, 32, 48]
+    assert [x["gates"] for x in r["tile_pass_by_gates"]] == [1, 2, 4, 8, 12, 16, 24, 32, 48] * 2
+    assert {x["k"] for x in r["tile_pass_by_gates"]} == {12, 13}
     assert all(x["gbs"] > 0 for x in r["tile_pass_by_gates"])
     assert r["zsum"]["launches"] == 1
 
