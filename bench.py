@@ -318,7 +318,7 @@ def costmodel_form(a):
     gates = config_circuit(2, n=a.n, layers=a.layers)
     cm = costmodel.CostModel(a.dtype, n_cal=26)
     t0 = time.perf_counter()
-    best, table = cm.choose(gates, a.n, ks=(9, 10, 11, 12), rs=(1, 4, 8, 16), reg_bits=(3, 4))
+    best, table = cm.choose(gates, a.n, ks=(9, 10, 11, 12, 13), rs=(1, 4, 8, 16), reg_bits=(3, 4))
     choose_s = time.perf_counter() - t0
     pick = table[:3] + table[3::max(1, (len(table) - 3) // 5)][:5]
     for row in pick:

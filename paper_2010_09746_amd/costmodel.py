@@ -173,7 +173,7 @@ class CostModel:
         prog.close()
         return self.predict_counts(counts, n, opts.get("k_tile", 10), opts.get("reg_bits", 0)), counts
 
-    def choose(self, gates, n: int, ks=(9, 10, 11, 12), rs=(1, 4, 8, 16), reg_bits=(0,),
+    def choose(self, gates, n: int, ks=(9, 10, 11, 12, 13), rs=(1, 4, 8, 16), reg_bits=(0,),
                perm_execs=("relabel",)) -> tuple:
         """Predicted-best options for this circuit and the table of predictions."""
         cands = []
