@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = the OpenMP default)")
+    ap.add_argument("--cal-n", type=int, default=27, help="costmodel: qubits of the calibration passes")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "tile_pass_traffic.json"))
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many GiB 3 times (a plain copy kernel of "
@@ -316,7 +317,7 @@ def costmodel_form(a):
     from workloads import config_circuit
 
     gates = config_circuit(2, n=a.n, layers=a.layers)
-    cm = costmodel.CostModel(a.dtype, n_cal=26)
+    cm = costmodel.CostModel(a.dtype, n_cal=a.cal_n)
     t0 = time.perf_counter()
     best, table = cm.choose(gates, a.n, ks=(9, 10, 11, 12, 13), rs=(1, 4, 8, 16), reg_bits=(3, 4))
     choose_s = time.perf_counter() - t0

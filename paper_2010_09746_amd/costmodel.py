@@ -80,7 +80,7 @@ def calibration_circuits(n: int, k: int, log_r: int, seed: int = 20100946 + 9) -
 class CostModel:
     """Measured costs per (amplitude type, k, register bits) tile shape."""
 
-    def __init__(self, dtype: str = "c128", n_cal: int = 26, perm_exec: str = "relabel", pinned: int = 3):
+    def __init__(self, dtype: str = "c128", n_cal: int = 27, perm_exec: str = "relabel", pinned: int = 3):
         self.dtype, self.n_cal, self.perm_exec, self.pinned = dtype, n_cal, perm_exec, pinned
         self.tile_costs = {}   # (k, reg_bits) -> {class: ms at n_cal}
         self.launch_costs = None
