@@ -346,3 +346,34 @@ def test_permute_position_exchanges_bit_exact(dt, pairs):
     st.permute(list(range(n)))
     raw = st.buffer.view(f).cpu().numpy().astype(np.float64)
     assert np.array_equal(raw[0::2] + 1j * raw[1::2], base)
+
+
+_SWEEP = np.random.default_rng(2010).integers(0, 10**6, size=24)
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_seeded_option_sweep(case):
+    """Seeded combinations of circuit family, size, tile size, exchange
+    bundle, pinned positions, executor, register shape and precision, each
+    against the oracle."""
+    rng = np.random.default_rng(int(_SWEEP[case]))
+    n = int(rng.integers(9, 18))
+    dt = ["c128", "c64"][int(rng.integers(0, 2))]
+    k = int(rng.integers(7, min(n, 14) + 1))
+    r = int(rng.choice([0, 1, 2, 4, 16]))
+    perm_exec = ["move", "relabel"][int(rng.integers(0, 2))]
+    pinned = int(rng.integers(0, min(3, k) + 1))
+    reg = int(rng.choice([0, 0, 2, 3, 4]))
+    fam = int(rng.integers(0, 3))
+    seed = int(rng.integers(0, 10**6))
+    g = (mixed_circuit(n, 12 * n, seed) if fam == 0 else
+         layered_circuit(n, int(rng.integers(3, 9)), seed=seed) if fam == 1 else qft_circuit(n))
+    _say(f"sweep {case}: n={n} {dt} k={k} r={r} {perm_exec} pinned={pinned} reg={reg} family={fam}")
+    st = Q.State(n, dt)
+    try:
+        st.run(g, form="pass", k_tile=k, max_swaps=r, pinned=pinned, perm_exec=perm_exec, reg_bits=reg)
+    except Q.QsimError as e:
+        # register shapes outside the instantiated ones are refused, not run
+        assert "not instantiated" in str(e), e
+        pytest.skip(f"shape not instantiated: {e}")
+    _check(st, O.run(g, n), dt)
