@@ -745,6 +745,16 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, con
         need(n_gates >= 0 && (n_gates == 0 || gates != nullptr), "bad arguments");
         const qs_run_opts o = opts ? *opts : default_opts();
         Program p;
+        // the plain form's program table, freed on every way out (after the
+        // stream has been synchronised)
+        struct FreeOps {
+            Program &p;
+            ~FreeOps()
+            {
+                if (p.d_ops)
+                    (void)hipFree(p.d_ops);
+            }
+        } free_ops{p};
         // every gate gives at most one operation and one re-layout, plus one
         // re-layout per segment
         const size_t bound = 3 * (size_t)n_gates + 16;
@@ -778,15 +788,15 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, con
             s->sigma = p.sigma_final;
         } else {
             compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p);
-            run_launches(s, p);
+            try {
+                run_launches(s, p);
+            } catch (...) {
+                (void)hipStreamSynchronize(s->stream);
+                throw;
+            }
         }
-        // the tables (and the staging the copies read) are reused next call;
-        // a program-owned table is freed with p
+        // the tables (and the staging the copies read) are reused next call
         hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-        if (p.d_ops) {
-            (void)hipFree(p.d_ops);
-            p.d_ops = nullptr;
-        }
     });
 }
 
