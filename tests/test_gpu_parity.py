@@ -272,12 +272,13 @@ def test_empty_circuit_and_identity_permutation():
 
 def test_config2_full_size_pass_vs_plain():
     n = 30
-    # the launch configuration bench.py times (k = 11, r = 16, relabel, 3 pinned)
-    _say("config-2 full size: pass (k=11, r=16, relabel) vs plain")
+    # the launch configuration bench.py times (k = 12, r = 16, relabel, 3
+    # pinned, the default register shape: 16 amplitudes per thread)
+    _say("config-2 full size: pass (k=12, r=16, relabel) vs plain")
     g = config_circuit(2)
     idx = config_samples(2)
     a = Q.State(n, "c128")
-    a.run(g, form="pass", k_tile=11, max_swaps=16, perm_exec="relabel", pinned=3)
+    a.run(g, form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=3)
     za, amp_a, na = a.expect_z(), a.amplitudes(idx), a.norm()
     a.close()
     del a
@@ -320,6 +321,35 @@ def test_precision_c128_oracle_28_qubits():
     st = Q.State(n, "c128").run(g, form="pass", k_tile=10, max_swaps=8, perm_exec="relabel", pinned=3)
     assert np.abs(st.amplitudes(idx) - ref[idx.astype(np.int64)]).max() <= 1e-12
     assert np.abs(st.expect_z() - O.expect_z(ref, n)).max() <= 1e-12
+
+
+def test_precision_full_size_32_qubits():
+    """The precision workload at full size (32 qubits, 50 layers) in the
+    launch configuration the benchmark times (k = 12, r = 16, relabel, 3
+    pinned): complex64 against complex128 within the stated bounds (fidelity
+    loss <= 1e-6, max |d amp| <= 1e-5), both norms 1, and the complex128 run
+    agrees with the plain complex128 gate-by-gate kernels on <Z_q> and on the
+    sampled amplitudes."""
+    n = 32
+    _say("precision full size: n=32 50 layers, c64 vs c128 (k=12, r=16)")
+    g = config_circuit(3)
+    idx = config_samples(3)
+    opts = dict(form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=3)
+    b = Q.State(n, "c128").run(g, **opts)
+    a = Q.State(n, "c64").run(g, **opts)
+    loss, mx = a.fidelity(b)
+    assert loss <= 1e-6 and mx <= 1e-5, (loss, mx)
+    assert abs(a.norm() - 1) <= 1e-5 and abs(b.norm() - 1) <= 1e-12
+    za, zb, amp_b = a.expect_z(), b.expect_z(), b.amplitudes(idx)
+    assert np.abs(za - zb).max() <= 1e-5
+    a.close()
+    del a
+    torch.cuda.empty_cache()
+    c = Q.State(n, "c128").run(g, form="plain")
+    assert np.abs(c.amplitudes(idx) - amp_b).max() <= 1e-12
+    assert np.abs(c.expect_z() - zb).max() <= 1e-12
+    c.close()
+    b.close()
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
