@@ -228,6 +228,7 @@ def serve(a):
     st = latency_summary(rec)
     nerr = [abs(res[r["id"]]["norm"] - 1.0) for r in reqs]
     main_stats = dict(srv.last_stats)
+    accuracy = served_accuracy(reqs, res, a.serve_k)
     sweep = []
     for rate in [float(x) for x in a.rate_sweep.split(",") if x.strip()]:
         tr = request_trace(count=a.sweep_requests, rate=rate)
@@ -244,11 +245,35 @@ def serve(a):
                                f"{a.serve_wg} workgroups per CU",
                    "parallelism": "1 GPU"},
         "latency": st, "server": main_stats,
-        "max_norm_error": float(np.max(nerr)),
+        "max_norm_error": float(np.max(nerr)), "accuracy": accuracy,
         "rate_sweep": sweep,
     }
     srv.close()
     print(json.dumps(line), flush=True)
+
+
+def served_accuracy(reqs, res, k, count=8):
+    """Error of the served complex64 results against complex128 runs of the
+    same circuits (pass form, one at a time), on `count` requests spread over
+    the trace: max |d<Z_q>| over all q and max |d amp| over the sampled
+    amplitudes."""
+    import numpy as np
+
+    from paper_2010_09746_amd import qsim as Q
+
+    pick = reqs[:: max(1, len(reqs) // count)][:count]
+    dz = da = 0.0
+    for r in pick:
+        ref = Q.State(r["n"], "c128")
+        ref.run(r["gates"], form="pass", k_tile=min(k, r["n"]), max_swaps=16, pinned=3, perm_exec="relabel")
+        z = ref.expect_z()
+        amps = ref.amplitudes(np.asarray(r["samples"], dtype=np.uint64))
+        ref.close()
+        got = res[r["id"]]
+        dz = max(dz, float(np.abs(z - got["z"]).max()))
+        da = max(da, float(np.abs(amps[: len(got["amps"])] - got["amps"]).max()))
+    return {"reference": "complex128 pass form, same circuit, run alone", "requests_checked": len(pick),
+            "qubits": [r["n"] for r in pick], "max_abs_expect_z": dz, "max_abs_amp": da}
 
 
 def _study_line(metric, value, unit, ms, cfg, body, hib=True, dtype="f64"):
