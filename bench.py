@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--sweep-requests", type=int, default=60)
     ap.add_argument("--serve-k", type=int, default=12, help="serve: tile qubits of the server")
     ap.add_argument("--serve-wg", type=int, default=16, help="serve: workgroups per CU of each step's launch")
+    ap.add_argument("--serve-solo-tiles", type=int, default=None,
+                    help="serve: passes with at least this many tiles run as launches of their own (0: never; "
+                         "default: the library's, 2^10)")
     ap.add_argument("--form", default="pass",
                     choices=["pass", "precision", "batch", "serve", "kernels", "qft", "random-family", "costmodel",
                              "ablation"],
@@ -221,7 +224,7 @@ def serve(a):
     trace = request_trace(count=a.requests, rate=a.rate)
     reqs = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in trace]
     srv = Server("c64", k_tile=a.serve_k, max_swaps=16, pinned=3, hbm_budget=200e9, max_slots=256,
-                 wg_per_cu=a.serve_wg)
+                 wg_per_cu=a.serve_wg, solo_tiles=a.serve_solo_tiles)
     # warm-up: one small request outside the measured trace
     srv.serve([dict(id=-1, arrival=0.0, n=12, gates=layered_circuit(12, 4, 1), samples=[0])], realtime=False)
     res, rec = srv.serve(reqs, realtime=True, log=lambda m: print("serve " + m, file=sys.stderr, flush=True))
@@ -242,7 +245,9 @@ def serve(a):
         "config": {"workload": f"serving form: Poisson trace {a.requests} requests at {a.rate}/s, n uniform in "
                                f"[12,30], depth uniform in [20,100], complex64 with FP64 reductions, 200 GB budget, "
                                f"<Z_q> all q + 16 sampled amplitudes per request; tile qubits {a.serve_k}, "
-                               f"{a.serve_wg} workgroups per CU",
+                               f"{a.serve_wg} workgroups per CU; passes of at least "
+                               f"{a.serve_solo_tiles if a.serve_solo_tiles is not None else 2 ** 10} tiles "
+                               f"as launches of their own (0: none)",
                    "parallelism": "1 GPU"},
         "latency": st, "server": main_stats,
         "max_norm_error": float(np.max(nerr)), "accuracy": accuracy,

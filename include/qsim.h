@@ -294,9 +294,11 @@ qs_status qs_batch_destroy(qs_batch *b);
 /* ---- serving form ------------------------------------------------------------ */
 
 /* A server keeps admitted requests' states resident and advances them by
- * continuous batching: every step is one launch that runs the next tile pass
- * of every resident request; requests join at step boundaries and leave when
- * their last pass has run and their read-out is copied to the host.
+ * continuous batching: every step runs the next tile pass of every resident
+ * request (one shared launch, plus a launch of its own for each request large
+ * enough to fill the device; see qs_server_set_solo_tiles); requests join at
+ * step boundaries and leave when their last pass has run and their read-out
+ * is copied to the host.
  *   dt, opts     amplitude type and pass options shared by all requests
  *                (opts->use_graph is ignored)
  *   hbm_budget   bytes of request states that may be resident at once
@@ -306,6 +308,14 @@ qs_status qs_batch_destroy(qs_batch *b);
  * operations and read-outs, and pinned host buffers for results. */
 qs_status qs_server_create(qs_dtype dt, const qs_batch_opts *opts, size_t hbm_budget, int max_slots,
                            int max_samples, qs_server **out);
+/* Requests whose passes have at least min_tiles tiles (2^(n - k_tile)) run
+ * each pass as a tile-pass launch of their own inside the step (one workgroup
+ * per tile, as qs_run_program does), after the shared launch of the smaller
+ * requests; 0: every pass goes into the shared launch.  Default 2^10 tiles
+ * (a pass of that many tiles fills the device by itself).
+ * Results do not depend on it.  QS_ERR_ARG for min_tiles < 0, QS_ERR_STATE
+ * while a step is in flight. */
+qs_status qs_server_set_solo_tiles(qs_server *s, int64_t min_tiles);
 qs_status qs_server_destroy(qs_server *s);
 /* 1 in *fits if a state of n qubits can be admitted now (budget and slots). */
 qs_status qs_server_fits(const qs_server *s, int n, int *fits);

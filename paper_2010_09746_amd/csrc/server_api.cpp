@@ -140,6 +140,9 @@ struct qs_server {
     std::vector<int64_t> finishing;
     bool pending = false;
     int64_t next_id = 1;
+    // a request whose pass has at least this many tiles runs it as a tile-pass
+    // launch of its own (one workgroup per tile) inside the step; 0: never
+    uint64_t solo_tiles = 1ull << 10;
 };
 
 namespace {
@@ -229,6 +232,17 @@ qs_status qs_server_create(qs_dtype dt, const qs_batch_opts *opts, size_t hbm_bu
             throw;
         }
         *out = s;
+    });
+}
+
+qs_status qs_server_set_solo_tiles(qs_server *s, int64_t min_tiles)
+{
+    return guard([&] {
+        if (!s || min_tiles < 0)
+            fail(QS_ERR_ARG, "bad arguments");
+        if (s->pending)
+            fail(QS_ERR_STATE, "a step is in flight");
+        s->solo_tiles = (uint64_t)min_tiles;
     });
 }
 
@@ -365,14 +379,19 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
         size_t ni = 0;
         int running = 0;
         s->finishing.clear();
+        std::vector<const BatchPass *> solo;
         for (int64_t id : s->active) {
             SReq &r = s->reqs.at(id);
             if (r.cur >= r.np)
                 continue;
             const uint32_t pi = (uint32_t)(r.pass_off + r.cur);
             const uint32_t nt = (uint32_t)(1ull << (r.n - s->K));
-            for (uint32_t t = 0; t < nt; t += chunk)
-                s->h_items[ni++] = BatchItem{pi, t, std::min(nt, t + chunk), 0};
+            if (s->solo_tiles && nt >= s->solo_tiles) {
+                solo.push_back(&r.passes[r.cur]);
+            } else {
+                for (uint32_t t = 0; t < nt; t += chunk)
+                    s->h_items[ni++] = BatchItem{pi, t, std::min(nt, t + chunk), 0};
+            }
             ++r.cur;
             ++running;
             if (r.cur == r.np)
@@ -392,6 +411,15 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
                 launch_batch_f32(a, s->log_r, s->log_nt, grid, s->stream);
             else
                 launch_batch_f64(a, s->log_r, s->log_nt, grid, s->stream);
+        }
+        // large passes fill the device by themselves: one workgroup per tile
+        // (streaming loads and stores where whole lines move) instead of the
+        // shared persistent launch
+        for (const BatchPass *P : solo) {
+            if (s->dt == QS_C64)
+                launch_tile_f32(P->t, P->ntiles, s->log_r, s->log_nt, s->stream);
+            else
+                launch_tile_f64(P->t, P->ntiles, s->log_r, s->log_nt, s->stream);
         }
         for (int64_t id : s->finishing) {
             SReq &r = s->reqs.at(id);

@@ -45,7 +45,7 @@ EXPORTS = [
     "qs_batch_create", "qs_batch_run", "qs_batch_results", "qs_batch_read_state", "qs_batch_get_stats",
     "qs_batch_synchronize", "qs_batch_destroy",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
-    "qs_server_step_wait", "qs_server_result", "qs_server_release",
+    "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
 ]
 
 
@@ -135,6 +135,7 @@ def load() -> ctypes.CDLL:
     L.qs_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(qs_batch_opts), ctypes.c_size_t, ctypes.c_int,
                                    ctypes.c_int, ctypes.POINTER(_vp)]
     L.qs_server_destroy.argtypes = [_vp]
+    L.qs_server_set_solo_tiles.argtypes = [_vp, ctypes.c_int64]
     L.qs_server_fits.argtypes = [_vp, ctypes.c_int, _ip]
     L.qs_server_admit.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -411,6 +412,11 @@ def qs_server_create(dtype, opts: qs_batch_opts, hbm_budget: int, max_slots: int
     _chk(load().qs_server_create(_dtype_code(dtype), ctypes.byref(opts), int(hbm_budget), max_slots, max_samples,
                                  ctypes.byref(h)))
     return h.value
+
+
+def qs_server_set_solo_tiles(h: int, min_tiles: int) -> None:
+    """Passes with at least min_tiles tiles run as launches of their own (0: never)."""
+    _chk(load().qs_server_set_solo_tiles(h, int(min_tiles)))
 
 
 def qs_server_destroy(h: int) -> None:

@@ -27,7 +27,7 @@ from . import qsim as Q
 
 class Server:
     def __init__(self, dtype="c64", k_tile=10, max_swaps=16, pinned=3, reg_bits=0, chunk=8, wg_per_cu=16,
-                 hbm_budget=200e9, max_slots=256, max_samples=16, compile_workers=8):
+                 hbm_budget=200e9, max_slots=256, max_samples=16, compile_workers=8, solo_tiles=None):
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
         self.dtype = dtype
@@ -37,6 +37,13 @@ class Server:
         opts = Q.make_batch_opts(k_tile=k_tile, max_swaps=max_swaps, pinned=pinned, reg_bits=reg_bits,
                                  chunk=chunk, wg_per_cu=wg_per_cu, use_graph=0)
         self.h = Q.qs_server_create(dtype, opts, int(hbm_budget), max_slots, max_samples)
+        if solo_tiles is not None:  # else the library's default
+            try:
+                Q.qs_server_set_solo_tiles(self.h, solo_tiles)
+            except Exception:
+                Q.qs_server_destroy(self.h)
+                self.h = None
+                raise
         self.pool = cf.ThreadPoolExecutor(max_workers=compile_workers)
 
     def close(self):

@@ -58,6 +58,30 @@ def test_results_same_alone_and_in_the_mix():
     srv.close()
 
 
+def test_large_requests_in_their_own_launch():
+    """Requests whose passes have at least the solo threshold of tiles run
+    each pass as a tile-pass launch of their own inside the step; the results
+    are those of the shared launch (complex64 tolerance) and of the oracle."""
+    _say("serving: solo launches for large requests")
+    reqs = _requests(12, 12, 17, 3, 8, seed=5)
+    out = {}
+    for solo in (0, 32):  # 0: all passes in the shared launch; 32: n >= 15 alone
+        srv = Server("c64", k_tile=10, max_swaps=8, pinned=3, reg_bits=3, max_slots=64, solo_tiles=solo)
+        res, _ = srv.serve(reqs, realtime=False)
+        out[solo] = res
+        srv.close()
+    assert any(r["n"] >= 15 for r in reqs) and any(r["n"] < 15 for r in reqs)
+    for r in reqs:
+        a, b = out[0][r["id"]], out[32][r["id"]]
+        assert np.abs(a["z"] - b["z"]).max() <= 1e-6
+        assert np.abs(a["amps"] - b["amps"]).max() <= 1e-6
+        ref = O.run(r["gates"], r["n"])
+        assert np.abs(b["z"] - O.expect_z(ref, r["n"])).max() <= 1e-5
+        assert np.abs(b["amps"] - ref[np.asarray(r["samples"], dtype=np.int64)]).max() <= 1e-5
+    with pytest.raises(Q.QsimError):
+        srv = Server("c64", k_tile=10, solo_tiles=-1)
+
+
 def test_budget_bounds_resident_states():
     _say("serving: budget")
     reqs = _requests(10, 16, 16, 4, 6, seed=4)
