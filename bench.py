@@ -200,8 +200,9 @@ def batch(a):
         "steps": a.steps, "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batching form: 256 seeded layered circuits, n uniform in [10,24], depth uniform in "
-                               "[10,60], complex64; one persistent launch under a HIP graph; output <Z_0> and norm "
-                               "per circuit", "parallelism": "1 GPU"},
+                               "[10,60], complex64; per pass level one shared persistent launch (large passes as "
+                               "tile-pass launches of their own), the sequence under a HIP graph; output <Z_0> and "
+                               "norm per circuit", "parallelism": "1 GPU"},
         "circuits_per_s": len(circuits) / sec,
         "tuned": best, "tune_seconds": tune_s, "tune_candidates": len(table),
         "batch_stats": st,

@@ -281,6 +281,13 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
  * pass level, then the per-circuit read-out.  With use_graph the whole
  * sequence is captured in a HIP graph on the first call and replayed after. */
 qs_status qs_batch_run(qs_batch *b);
+/* Passes with at least min_tiles tiles (2^(n - k_tile)), other than each
+ * circuit's last, run as tile-pass launches of their own (one workgroup per
+ * tile) after their level's launch; 0: every pass in the level launches.
+ * Default 2^12 tiles.  Waits for the last run; the next qs_batch_run captures
+ * the new launch sequence.  Results do not depend on it.  QS_ERR_ARG for
+ * min_tiles < 0. */
+qs_status qs_batch_set_solo_tiles(qs_batch *b, int64_t min_tiles);
 /* Wait for the last run; z0[c] = <Z_0> and norms[c] = sum |a|^2 of circuit c
  * (host arrays of count doubles, FP64 accumulation; either may be NULL). */
 qs_status qs_batch_results(qs_batch *b, double *z0, double *norms);

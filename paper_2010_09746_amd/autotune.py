@@ -1,9 +1,9 @@
 """Autotuner for the batching form.
 
 Chooses the tile size k, the exchanges per permutation r (which sets the
-fusion depth: gates per tile pass), the register bits per thread and the
-persistent launch shape by timing graph replays of the actual batch on the
-device.  Results are cached in JSON keyed by device name, amplitude type and a
+fusion depth: gates per tile pass), the register bits per thread, the
+persistent launch shape and which large passes run as launches of their own,
+by timing graph replays of the actual batch on the device.  Results are cached in JSON keyed by device name, amplitude type and a
 signature of the workload (qubit-count histogram and gate count).
 """
 
@@ -108,6 +108,14 @@ def tune_batch(circuits, dtype="c64", cache_path=DEFAULT_CACHE, reps=2, refresh=
             table.append((o, t))
             if log:
                 log(f"{o} -> {t * 1e3:.2f} ms")
+    best = min(table, key=lambda x: x[1])[0]
+    # stage 3: which passes run as launches of their own (tiles threshold)
+    for solo in (0, 1 << 10, 1 << 12, 1 << 14):
+        o = dict(best, solo_tiles=solo)
+        t, _ = _time(circuits, dtype, o, reps)
+        table.append((o, t))
+        if log:
+            log(f"{o} -> {t * 1e3:.2f} ms")
     best = min(table, key=lambda x: x[1])[0]
     cache[key] = dict(best=best, table=table)
     _save(cache_path, cache)

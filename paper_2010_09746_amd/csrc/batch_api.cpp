@@ -27,6 +27,10 @@ struct qs_batch {
     std::vector<BatchPass> passes;
     std::vector<BatchItem> items;
     std::vector<uint32_t> level_start;  // items of level L: [level_start[L], level_start[L+1])
+    std::vector<std::vector<int>> circ_passes;  // pass indices of each circuit, in order
+    std::vector<std::vector<int>> level_solo;   // passes of level L run as launches of their own
+    uint64_t solo_tiles = 1ull << 12;           // 0: every pass in the level launch
+    size_t items_cap = 0;                       // BatchItem capacity of d_items
     std::vector<TileOp> ops;
     std::vector<uint64_t> part_off;
     std::vector<uint32_t> part_cnt;
@@ -97,6 +101,39 @@ template <typename F> qs_status guard(F &&f)
     }
 }
 
+// Work items of each pass level.  A pass of at least solo_tiles tiles that is
+// not its circuit's last (the last one also produces the read-out partials)
+// goes to level_solo instead: it fills the device by itself and runs as a
+// tile-pass launch (one workgroup per tile) after the level launch.
+void build_levels(qs_batch *b)
+{
+    const uint32_t chunk = (uint32_t)std::max(1, b->opts.chunk);
+    size_t max_np = 0;
+    for (auto &v : b->circ_passes)
+        max_np = std::max(max_np, v.size());
+    b->items.clear();
+    b->level_start.clear();
+    b->level_solo.assign(max_np, {});
+    for (size_t lvl = 0; lvl < max_np; ++lvl) {
+        b->level_start.push_back((uint32_t)b->items.size());
+        for (int c = 0; c < b->count; ++c) {
+            if (lvl >= b->circ_passes[c].size())
+                continue;
+            const int pi = b->circ_passes[c][lvl];
+            const BatchPass &P = b->passes[pi];
+            const uint32_t nt = P.ntiles;
+            if (b->solo_tiles && nt >= b->solo_tiles && !P.last) {
+                b->level_solo[lvl].push_back(pi);
+                continue;
+            }
+            for (uint32_t t = 0; t < nt; t += chunk)
+                b->items.push_back(BatchItem{(uint32_t)pi, t, std::min(nt, t + chunk), 0});
+        }
+    }
+    b->level_start.push_back((uint32_t)b->items.size());
+    b->stats.n_items = (int64_t)b->items.size();
+}
+
 void enqueue(qs_batch *b)
 {
     launch_batch_init(b->d_state, b->dt, b->total, b->d_starts, b->count, b->stream);
@@ -108,12 +145,19 @@ void enqueue(qs_batch *b)
         a.i1 = b->level_start[L + 1];
         a.partials = b->d_partials;
         const int grid = (int)std::min<uint32_t>((uint32_t)b->grid, a.i1 - a.i0);
-        if (grid <= 0)
-            continue;
-        if (b->dt == QS_C64)
-            launch_batch_f32(a, b->log_r, b->log_nt, grid, b->stream);
-        else
-            launch_batch_f64(a, b->log_r, b->log_nt, grid, b->stream);
+        if (grid > 0) {
+            if (b->dt == QS_C64)
+                launch_batch_f32(a, b->log_r, b->log_nt, grid, b->stream);
+            else
+                launch_batch_f64(a, b->log_r, b->log_nt, grid, b->stream);
+        }
+        for (int pi : b->level_solo[L]) {
+            const BatchPass &P = b->passes[pi];
+            if (b->dt == QS_C64)
+                launch_tile_f32(P.t, P.ntiles, b->log_r, b->log_nt, b->stream);
+            else
+                launch_tile_f64(P.t, P.ntiles, b->log_r, b->log_nt, b->stream);
+        }
     }
     launch_batch_reduce(b->d_partials, b->d_part_off, b->d_part_cnt, b->count, b->d_out, b->stream);
 }
@@ -231,23 +275,9 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
                 b->stats.n_perm += p.stats.n_perm;
             }
             // work items ordered by pass level
-            const uint32_t chunk = (uint32_t)std::max(1, o.chunk);
-            size_t max_np = 0;
-            for (auto &v : circ_passes)
-                max_np = std::max(max_np, v.size());
-            for (size_t lvl = 0; lvl < max_np; ++lvl) {
-                b->level_start.push_back((uint32_t)b->items.size());
-                for (int c = 0; c < count; ++c) {
-                    if (lvl >= circ_passes[c].size())
-                        continue;
-                    const int pi = circ_passes[c][lvl];
-                    const uint32_t nt = b->passes[pi].ntiles;
-                    for (uint32_t t = 0; t < nt; t += chunk)
-                        b->items.push_back(BatchItem{(uint32_t)pi, t, std::min(nt, t + chunk), 0});
-                }
-            }
-            b->level_start.push_back((uint32_t)b->items.size());
-            b->stats.n_items = (int64_t)b->items.size();
+            b->circ_passes = std::move(circ_passes);
+            build_levels(b);
+            b->items_cap = std::max<size_t>(1, b->items.size());
 
             if (!b->ops.empty())
                 hipchk(hipMemcpy(b->d_ops, b->ops.data(), b->ops.size() * sizeof(TileOp), hipMemcpyHostToDevice),
@@ -274,6 +304,34 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
         auto t1 = std::chrono::steady_clock::now();
         b->stats.compile_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         *out = b;
+    });
+}
+
+qs_status qs_batch_set_solo_tiles(qs_batch *b, int64_t min_tiles)
+{
+    return guard([&] {
+        if (!b || min_tiles < 0)
+            fail(QS_ERR_ARG, "bad arguments");
+        hipchk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        b->solo_tiles = (uint64_t)min_tiles;
+        build_levels(b);
+        if (b->items.size() > b->items_cap) {
+            hipchk(hipFree(b->d_items), "hipFree(batch items)");
+            b->d_items = nullptr;
+            hipchk(hipMalloc(&b->d_items, b->items.size() * sizeof(BatchItem)), "hipMalloc(batch items)");
+            b->items_cap = b->items.size();
+        }
+        if (!b->items.empty())
+            hipchk(hipMemcpy(b->d_items, b->items.data(), b->items.size() * sizeof(BatchItem),
+                             hipMemcpyHostToDevice),
+                   "hipMemcpy(batch items)");
+        // the captured launch sequence no longer matches: capture again at the next run
+        if (b->exec)
+            hipchk(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
+        b->exec = nullptr;
+        if (b->graph)
+            hipchk(hipGraphDestroy(b->graph), "hipGraphDestroy");
+        b->graph = nullptr;
     });
 }
 

@@ -43,7 +43,7 @@ EXPORTS = [
     "qs_program_instructions", "qs_run_program", "qs_run_circuit", "qs_read_amplitudes", "qs_read_state",
     "qs_expect_z", "qs_norm", "qs_fidelity", "qs_synchronize", "qs_profile_enable", "qs_profile_read",
     "qs_batch_create", "qs_batch_run", "qs_batch_results", "qs_batch_read_state", "qs_batch_get_stats",
-    "qs_batch_synchronize", "qs_batch_destroy",
+    "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_set_solo_tiles",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
     "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
 ]
@@ -136,6 +136,7 @@ def load() -> ctypes.CDLL:
                                    ctypes.c_int, ctypes.POINTER(_vp)]
     L.qs_server_destroy.argtypes = [_vp]
     L.qs_server_set_solo_tiles.argtypes = [_vp, ctypes.c_int64]
+    L.qs_batch_set_solo_tiles.argtypes = [_vp, ctypes.c_int64]
     L.qs_server_fits.argtypes = [_vp, ctypes.c_int, _ip]
     L.qs_server_admit.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -576,14 +577,26 @@ class Program:
 class Batch:
     """Many circuits (list of (n, gates)) run by one persistent launch."""
 
-    def __init__(self, circuits, dtype="c64", **opts):
+    def __init__(self, circuits, dtype="c64", solo_tiles=None, **opts):
         self.ns = [int(n) for n, _ in circuits]
         self.count = len(self.ns)
         self.opts = dict(opts)
         self.h = qs_batch_create(circuits, dtype, make_batch_opts(**opts))
+        if solo_tiles is not None:  # else the library's default
+            try:
+                self.set_solo_tiles(solo_tiles)
+            except Exception:
+                self.close()
+                raise
 
     def run(self) -> "Batch":
         qs_batch_run(self.h)
+        return self
+
+    def set_solo_tiles(self, min_tiles: int) -> "Batch":
+        """Passes of at least min_tiles tiles (not a circuit's last) run as
+        launches of their own; 0: none."""
+        _chk(load().qs_batch_set_solo_tiles(self.h, int(min_tiles)))
         return self
 
     def results(self):

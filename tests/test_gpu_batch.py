@@ -95,6 +95,39 @@ def test_graph_replays_are_identical():
     g.close()
 
 
+@pytest.mark.parametrize("dt,tol", [("c64", 1e-5), ("c128", 1e-12)])
+def test_large_passes_in_their_own_launches(dt, tol):
+    """Passes of at least the solo threshold of tiles run as tile-pass
+    launches of their own, in the captured graph and eagerly: the results are
+    those of the level launches alone, replay after replay, and the oracle's."""
+    _say(f"batch solo launches {dt}")
+    circ = _small_batch(seed=11, count=14, n_lo=10, n_hi=17)
+    assert any(n >= 15 for n, _ in circ) and any(n < 15 for n, _ in circ)
+    base = Q.Batch(circ, dt, k_tile=10, max_swaps=4, wg_per_cu=4, chunk=4, use_graph=0, solo_tiles=0)
+    z0, n0 = base.run().results()
+    s0 = [base.state(c) for c in range(len(circ))]
+    base.close()
+    for graph in (0, 1):
+        b = Q.Batch(circ, dt, k_tile=10, max_swaps=4, wg_per_cu=4, chunk=4, use_graph=graph)
+        b.run().results()
+        b.set_solo_tiles(32)  # circuits of 15 qubits and more: 32+ tiles of 2^10
+        for rep in range(3):
+            z, nrm = b.run().results()
+            assert np.abs(z - z0).max() <= tol and np.abs(nrm - n0).max() <= tol, (graph, rep)
+        for c, (n, g) in enumerate(circ):
+            assert np.abs(b.state(c) - s0[c]).max() <= tol
+            if c % 4 == 0:
+                assert np.abs(b.state(c) - O.run(g, n)).max() <= tol
+        b.set_solo_tiles(0)
+        z, nrm = b.run().results()
+        assert np.abs(z - z0).max() <= tol
+        b.close()
+    b = Q.Batch(circ[:2], dt, k_tile=10)
+    with pytest.raises(Q.QsimError):
+        b.set_solo_tiles(-1)
+    b.close()
+
+
 def test_batch_workload_shape_subset():
     """A slice of the 256-circuit workload (uneven sizes up to 20 qubits)."""
     _say("batch workload slice")
