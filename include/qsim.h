@@ -271,7 +271,8 @@ typedef struct {
 /* Compile count circuits (circuit c: n_qubits[c] qubits, gates[c] a host array
  * of n_gates[c] gates) for execution together.  Circuits advance one pass
  * level at a time: level L holds every circuit's L-th tile pass, and one
- * persistent launch strides over the tiles of a level.  The library allocates
+ * persistent launch strides over the tiles of a level (large passes run as
+ * launches of their own; see qs_batch_set_solo_tiles).  The library allocates
  * one device buffer holding every state (complex64 or complex128), the
  * compiled pass tables and its own HIP stream.  Compilation runs on host
  * threads. */
