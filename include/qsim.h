@@ -279,8 +279,9 @@ typedef struct {
 qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *gates, const int64_t *n_gates,
                           qs_dtype dt, const qs_batch_opts *opts, qs_batch **out);
 /* Enqueue one execution: every state set to |0...0>, one persistent launch per
- * pass level, then the per-circuit read-out.  With use_graph the whole
- * sequence is captured in a HIP graph on the first call and replayed after. */
+ * pass level (followed by the launches of that level's large passes), then
+ * the per-circuit read-out.  With use_graph the whole sequence is captured in
+ * a HIP graph on the first call and replayed after. */
 qs_status qs_batch_run(qs_batch *b);
 /* Passes with at least min_tiles tiles (2^(n - k_tile)), other than each
  * circuit's last, run as tile-pass launches of their own (one workgroup per
