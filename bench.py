@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--r", type=int, default=16)
     ap.add_argument("--perm-exec", default="relabel")
     ap.add_argument("--pinned", type=int, default=3)
+    ap.add_argument("--pinned-c64", type=int, default=4,
+                    help="pinned positions for complex64 runs (precision and serving forms): 4 keeps the "
+                         "lowest 16 amplitudes, one 128-byte line, in every tile")
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
@@ -132,7 +135,8 @@ def precision(a):
     states = {}
     for dt, k in (("c64", a.k), ("c128", a.k)):
         st = Q.State(n, dt)
-        opts = dict(form="pass", k_tile=k, max_swaps=a.r, perm_exec="relabel", pinned=a.pinned)
+        pin = a.pinned_c64 if (dt == "c64" and a.pinned_c64 is not None) else a.pinned
+        opts = dict(form="pass", k_tile=k, max_swaps=a.r, perm_exec="relabel", pinned=pin)
         st.run(gates, **opts)  # warm-up
         torch.cuda.synchronize()
         ts = []
@@ -224,7 +228,8 @@ def serve(a):
 
     trace = request_trace(count=a.requests, rate=a.rate)
     reqs = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in trace]
-    srv = Server("c64", k_tile=a.serve_k, max_swaps=16, pinned=3, hbm_budget=200e9, max_slots=256,
+    srv = Server("c64", k_tile=a.serve_k, max_swaps=16,
+                 pinned=a.pinned_c64 if a.pinned_c64 is not None else a.pinned, hbm_budget=200e9, max_slots=256,
                  wg_per_cu=a.serve_wg, solo_tiles=a.serve_solo_tiles)
     # warm-up: one small request outside the measured trace
     srv.serve([dict(id=-1, arrival=0.0, n=12, gates=layered_circuit(12, 4, 1), samples=[0])], realtime=False)
