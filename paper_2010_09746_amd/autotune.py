@@ -2,8 +2,9 @@
 
 Chooses the tile size k, the exchanges per permutation r (which sets the
 fusion depth: gates per tile pass), the register bits per thread, the
-persistent launch shape and which large passes run as launches of their own,
-by timing graph replays of the actual batch on the device.  Results are cached in JSON keyed by device name, amplitude type and a
+persistent launch shape, the pinned positions and which large passes run as
+launches of their own, by timing graph replays of the actual batch on the
+device.  Results are cached in JSON keyed by device name, amplitude type and a
 signature of the workload (qubit-count histogram and gate count).
 """
 
@@ -109,7 +110,18 @@ def tune_batch(circuits, dtype="c64", cache_path=DEFAULT_CACHE, reps=2, refresh=
             if log:
                 log(f"{o} -> {t * 1e3:.2f} ms")
     best = min(table, key=lambda x: x[1])[0]
-    # stage 3: which passes run as launches of their own (tiles threshold)
+    # stage 3: pinned positions (a 128-byte line is 8 complex128 or 16
+    # complex64 amplitudes: 3 or 4 positions), then which passes run as
+    # launches of their own (tiles threshold)
+    for pin in (3, 4):
+        o = dict(best, pinned=pin)
+        if o == best or (pin == 4 and Q.elem_bytes(dtype) != 8):
+            continue
+        t, _ = _time(circuits, dtype, o, reps)
+        table.append((o, t))
+        if log:
+            log(f"{o} -> {t * 1e3:.2f} ms")
+    best = min(table, key=lambda x: x[1])[0]
     for solo in (0, 1 << 10, 1 << 12, 1 << 14):
         o = dict(best, solo_tiles=solo)
         t, _ = _time(circuits, dtype, o, reps)
