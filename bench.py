@@ -149,7 +149,7 @@ def precision(a):
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         ms = float(np.median(ts))
-        out[dt] = dict(ms_per_step=ms * 1e3, value=upd / ms, k_tile=k, norm=st.norm())
+        out[dt] = dict(ms_per_step=ms * 1e3, value=upd / ms, k_tile=k, pinned=pin, max_swaps=a.r, norm=st.norm())
         states[dt] = (st, z, amp)
         print(f"{dt}: {ms * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
     loss, mx = states["c64"][0].fidelity(states["c128"][0])
