@@ -291,6 +291,28 @@ def test_config2_full_size_pass_vs_plain():
     assert np.abs(za - zb).max() <= 1e-12
 
 
+@pytest.mark.parametrize("dt,n,pinned", [("c128", 24, 3), ("c64", 22, 4)])
+def test_bench_launch_configuration_vs_oracle(dt, n, pinned):
+    """The launch configuration bench.py times (k = 12, r = 16, relabelled
+    placements, the default register shape: 16 amplitudes per thread; 3
+    pinned positions for complex128, 4 for complex64) on the benchmark's
+    circuit family at a size where 10-12 qubits lie outside the tile, so that
+    PermuteQubits bundles of many exchanges form; full vector against the
+    oracle."""
+    _say(f"bench configuration vs oracle {dt} n={n} pinned={pinned}")
+    g = config_circuit(2, n=n)
+    opts = dict(form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=pinned)
+    P = Q.Program(g, n, dt, **opts)
+    ps = P.stats()
+    P.close()
+    assert ps["n_swaps"] >= 2 * ps["n_perm"] > 0  # exchanges are bundled
+    ref = O.run(g, n)
+    st = Q.State(n, dt).run(g, **opts)
+    _check(st, ref, dt)
+    assert np.abs(st.expect_z() - O.expect_z(ref, n)).max() <= TOL[dt]
+    st.close()
+
+
 # ---------------------------------------------------------------------------
 # precision form: complex64 bulk with FP64 read-out against complex128
 

@@ -123,7 +123,7 @@ def test_default_register_shape_at_large_tiles(dt, k):
     reqs = _requests(6, k, k + 3, 3, 8, seed=11)
     srv = Server(dt, k_tile=k, max_swaps=8, pinned=3, max_slots=16)
     res, _ = srv.serve(reqs, realtime=False)
-    tol = 1e-10 if dt == "c128" else 1e-5
+    tol = 1e-12 if dt == "c128" else 1e-5
     for r in reqs:
         n, g = r["n"], r["gates"]
         ref = O.run(g, n)

@@ -210,6 +210,89 @@ def test_tiny_pass_is_valid_greedy_and_exact(seed):
     assert np.abs(O.to_logical(v, n, sig) - O.run(g, n, x=3)).max() < 1e-13
 
 
+def _greedy_chain_ends(g, preds, done, sigma, m, r, pinned):
+    """Every placement that a chain of single local<->global exchanges can
+    reach from sigma when each exchange is one of the highest-scoring single
+    exchanges (any tie-break), scores strictly more than the count reached
+    before it, never moves a qubit out of the first `pinned` positions, and the
+    chain stops only at r exchanges or when no exchange scores higher."""
+    n = len(sigma)
+    ends = set()
+
+    def walk(cur, base, depth):
+        cands = []
+        for a in range(n):
+            if not (pinned <= cur[a] < m):
+                continue
+            for b in range(n):
+                if cur[b] >= m:
+                    s2 = list(cur)
+                    s2[a], s2[b] = cur[b], cur[a]
+                    cands.append((_closure(g, preds, done, s2, m), s2))
+        top = max((c for c, _ in cands), default=-1)
+        if depth == r or top <= base:
+            if depth > 0:
+                ends.add(tuple(cur))
+            return
+        for c, s2 in cands:
+            if c == top:
+                walk(s2, c, depth + 1)
+
+    walk(list(sigma), 0, 0)
+    return ends
+
+
+@pytest.mark.parametrize("r,pinned,seed", [(2, 0, 0), (2, 1, 1), (3, 0, 2), (3, 1, 3), (4, 0, 4), (4, 2, 5),
+                                           (2, 0, 6), (3, 2, 7)])
+def test_tiny_bundled_pass_is_valid_greedy_chain(r, pinned, seed):
+    _check_bundled_pass(r, pinned, seed)
+
+
+def _check_bundled_pass(r, pinned, seed):
+    """r > 1 (up to r exchanges in one PermuteQubits): brute force over every
+    single exchange at every link of the chain.  Each exchange must strictly
+    raise the closure count reached by the exchanges before it, no single
+    exchange from the same placement may score higher, the chain ends at r
+    exchanges or when nothing scores higher, and qubits at the pinned
+    positions never move.  The compiled program computes the plain result."""
+    n, m = 6, 3 + seed % 2
+    g = mixed_circuit(n, 36, seed=2000 + seed) if seed % 3 else paper_random_circuit(n, 40, 0.3, seed=2000 + seed)
+    ins, st = O.pass_ref(g, n, m, r=r, pinned=pinned)
+    preds = {v: set() for v in range(len(g))}
+    for h, v in O.dag_edges(g):
+        preds[v].add(h)
+    sigma, done, bundles = list(range(n)), set(), 0
+    for op, arg in ins:
+        if op == "perm":
+            assert _closure(g, preds, done, sigma, m) == 0
+            for q in range(n):
+                if sigma[q] < pinned:
+                    assert arg[q] == sigma[q]
+            assert tuple(arg) in _greedy_chain_ends(g, preds, done, sigma, m, r, pinned)
+            moved = sum(1 for q in range(n) if arg[q] != sigma[q])
+            bundles += moved > 2
+            sigma = list(arg)
+        else:
+            assert arg not in done and preds[arg] <= done
+            if op == "apply":
+                assert _local(g[arg], sigma, m)
+            done.add(arg)
+    assert done == set(range(len(g)))
+    assert st["swaps"] >= st["perm"]
+    v, sig = O.run_program(g, n, ins, x=5)
+    assert np.abs(O.to_logical(v, n, sig) - O.run(g, n, x=5)).max() < 1e-13
+    return bundles
+
+
+def test_bundled_pass_forms_bundles():
+    """The brute-force cases above include PermuteQubits of several
+    exchanges (the chain is exercised, not only its r = 1 prefix)."""
+    total = 0
+    for r, pinned, seed in [(2, 0, 0), (3, 0, 2), (4, 0, 4), (2, 0, 6)]:
+        total += _check_bundled_pass(r, pinned, seed)
+    assert total > 0
+
+
 @pytest.mark.parametrize("r,pinned", [(2, 0), (3, 1), (1, 2)])
 def test_pass_extensions_keep_the_state(r, pinned):
     n, m = 7, 4
