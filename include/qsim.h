@@ -224,6 +224,26 @@ qs_status qs_run_program(qs_state *s, const qs_program *p);
 qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates,
                          const qs_run_opts *opts);
 
+/* ---- allocation-free run -------------------------------------------------- */
+
+/* Tile operations a program run by qs_run_program_noalloc may hold. */
+#define QS_NOALLOC_MAX_OPS 32768
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the launches
+ * of qs_run_program, with the program's operation table copied (on the
+ * state's stream) into a fixed array of the library instead of a device
+ * buffer allocated on first run.  Calls no hipMalloc, hipFree or other
+ * allocating routine.  The array holds QS_NOALLOC_MAX_OPS records of 104
+ * bytes (3.25 MiB); each device the library runs on keeps its own copy until
+ * the process ends.  Every call on a device overwrites it: calls on one
+ * stream are ordered, calls that overlap on one device (other streams or
+ * threads) race.  The state's device must be the current device
+ * (QS_ERR_STATE otherwise).  QS_ERR_ARG for a program with more than
+ * QS_NOALLOC_MAX_OPS tile operations; the other checks and errors are those
+ * of qs_run_program. */
+qs_status qs_run_program_noalloc(qs_state *s, const qs_program *p);
+
 /* ---- read-out (FP64 accumulation) --------------------------------------- */
 
 /* Amplitudes at count logical indices (host array) into out (host, 2*count

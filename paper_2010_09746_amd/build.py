@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libqsim.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["api.cpp", "batch_api.cpp", "server_api.cpp", "gates.hip", "readout.hip", "tile_f32.hip", "tile_f64.hip",
-               "batch_f32.hip", "batch_f64.hip"]
+               "batch_f32.hip", "batch_f64.hip", "noalloc.hip"]
 CXX_SOURCES = ["compiler.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

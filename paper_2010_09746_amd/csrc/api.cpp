@@ -394,12 +394,17 @@ void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, con
     }
 }
 
-void run_launches(qs_state *s, Program &p)
+void check_program_fits(const qs_state *s, const Program &p)
 {
     need(s->n == p.n, "program compiled for a different qubit count");
     need(s->dt == p.dt, "program compiled for a different amplitude type");
     if (s->sigma != p.sigma0)
         fail(QS_ERR_STATE, "state placement differs from the program's starting placement");
+}
+
+void run_launches(qs_state *s, Program &p)
+{
+    check_program_fits(s, p);
     upload_ops(p);
     launch_range(s, p, 0, p.launches.size(), p.d_ops);
     s->sigma = p.sigma_final;
@@ -436,6 +441,28 @@ qs_run_opts default_opts()
 }
 
 }  // namespace
+
+namespace qsim {
+
+void check_program_on(const qs_state *s, const Program &p)
+{
+    need(s != nullptr, "state is NULL");
+    check_program_fits(s, p);
+}
+
+void run_program_with_ops(qs_state *s, const Program &p, const TileOp *d_ops)
+{
+    check_program_on(s, p);
+    launch_range(s, p, 0, p.launches.size(), d_ops);
+    s->sigma = p.sigma_final;
+}
+
+void *state_stream(const qs_state *s) { return s->stream; }
+int state_device(const qs_state *s) { return s->dev; }
+
+qs_status guarded(const std::function<void()> &f) { return guard(f); }
+
+}  // namespace qsim
 
 extern "C" {
 

@@ -171,6 +171,21 @@ void tile_shape(int k, qs_dtype dt, int reg_bits_opt, int *log_r, int *log_nt);
 int pass_reg_bits(int k, qs_dtype dt);
 
 // ---------------------------------------------------------------------------
+// state access for entry points defined outside api.cpp
+
+// The checks of qs_run_program (qubit count, amplitude type, starting
+// placement) without running anything.
+void check_program_on(const qs_state *s, const Program &p);
+// Enqueue every launch of p on the state's stream with the operation table
+// read from d_ops (device memory holding p.ops), then take p's final
+// placement.  Allocates nothing on the device.
+void run_program_with_ops(qs_state *s, const Program &p, const TileOp *d_ops);
+void *state_stream(const qs_state *s);  // the state's hipStream_t
+int state_device(const qs_state *s);    // the device the state was created on
+// f() with exceptions turned into a status and the per-thread message
+qs_status guarded(const std::function<void()> &f);
+
+// ---------------------------------------------------------------------------
 // error reporting
 
 struct Error {

@@ -28,6 +28,7 @@ QS_C64, QS_C128 = 0, 1
 QS_FORM_PLAIN, QS_FORM_PASS = 0, 1
 QS_PERM_MOVE, QS_PERM_RELABEL = 0, 1
 QS_GATE_U, QS_GATE_CX, QS_GATE_CZ, QS_GATE_CU = 0, 1, 2, 3
+NOALLOC_MAX_OPS = 32768  # QS_NOALLOC_MAX_OPS
 
 STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_OOM", -3: "QS_ERR_BUDGET", -4: "QS_ERR_HIP",
           -5: "QS_ERR_UNSUPPORTED", -6: "QS_ERR_STATE"}
@@ -46,6 +47,7 @@ EXPORTS = [
     "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_set_solo_tiles",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
     "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
+    "qs_run_program_noalloc",
 ]
 
 
@@ -117,6 +119,7 @@ def load() -> ctypes.CDLL:
     L.qs_program_instructions.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
                                           ctypes.POINTER(ctypes.c_int64)]
     L.qs_run_program.argtypes = [_vp, _vp]
+    L.qs_run_program_noalloc.argtypes = [_vp, _vp]
     L.qs_run_circuit.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.POINTER(qs_run_opts)]
     L.qs_read_amplitudes.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
     L.qs_read_state.argtypes = [_vp, _vp]
@@ -297,6 +300,10 @@ def qs_program_instructions(h: int, n: int):
 
 def qs_run_program(h: int, prog: int) -> None:
     _chk(load().qs_run_program(h, prog))
+
+
+def qs_run_program_noalloc(h: int, prog: int) -> None:
+    _chk(load().qs_run_program_noalloc(h, prog))
 
 
 def qs_run_circuit(h: int, gates, opts: qs_run_opts | None = None) -> None:
@@ -518,8 +525,8 @@ class State:
         qs_run_circuit(self.h, gates, make_opts(**opts))
         return self
 
-    def run_program(self, prog: "Program") -> "State":
-        qs_run_program(self.h, prog.h)
+    def run_program(self, prog: "Program", noalloc: bool = False) -> "State":
+        (qs_run_program_noalloc if noalloc else qs_run_program)(self.h, prog.h)
         return self
 
     # read-out

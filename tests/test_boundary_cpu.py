@@ -31,6 +31,12 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_noalloc_limit_agrees_with_header():
+    txt = open(os.path.join(ROOT, "include", "qsim.h")).read()
+    m = re.search(r"#define QS_NOALLOC_MAX_OPS (\d+)", txt)
+    assert m and int(m.group(1)) == Q.NOALLOC_MAX_OPS
+
+
 def test_gate_record_layout():
     assert Q.GATE_DTYPE.itemsize == 80
     assert Q.GATE_DTYPE.fields["u"][1] == 16
