@@ -98,7 +98,17 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *   max_fuse   upper bound on gates per tile pass (0 = none).
  *   reg_bits   amplitudes per thread = 2^reg_bits inside the tile kernel
  *              (0 = chosen by the library).
+ *   flags      QS_OPT_FULL_MATRICES: every one-qubit gate of a tile pass is
+ *              applied as its whole 2x2 matrix.  Without it (0, the
+ *              default) an uncontrolled gate M on qubit q is factored as
+ *              M = e^{i phi} diag(1, e^{i theta}) W, W = [[a, -conj(b)],
+ *              [b, a]] with a real (12 real multiply-adds per amplitude pair
+ *              instead of 16); diag(1, e^{i theta}) is kept pending on q
+ *              and absorbed by q's next one-qubit gate, or applied before an
+ *              operation that acts on q non-diagonally, and the scalar is
+ *              folded into the last gate.  Same result up to rounding.
  */
+enum { QS_OPT_FULL_MATRICES = 1 };
 typedef struct {
     int32_t form;
     int32_t k_tile;
@@ -107,7 +117,7 @@ typedef struct {
     int32_t perm_exec;
     int32_t max_fuse;
     int32_t reg_bits;
-    int32_t reserved;
+    int32_t flags;
 } qs_run_opts;
 
 typedef struct {
@@ -185,6 +195,8 @@ qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
  *   QS_OPC_PLAIN_*     one-gate launches by gate kind
  *   QS_OPC_MOVE        data-movement launches, QS_OPC_MOVE_FRACTION the sum
  *                      of the fractions of amplitudes they move
+ *   QS_OPC_W           one-qubit updates in the reduced form W (see flags)
+ *   QS_OPC_PHASE       pending phases applied on their own (see flags)
  * Writes min(cap, QS_OPC_COUNT) entries. */
 enum {
     QS_OPC_TILE_PASS = 0,
@@ -202,7 +214,9 @@ enum {
     QS_OPC_PLAIN_CZ = 12,
     QS_OPC_MOVE = 13,
     QS_OPC_MOVE_FRACTION = 14,
-    QS_OPC_COUNT = 15
+    QS_OPC_W = 15,         /* reduced one-qubit update W */
+    QS_OPC_PHASE = 16,     /* pending phase applied on its own */
+    QS_OPC_COUNT = 17
 };
 qs_status qs_program_op_counts(const qs_program *p, double *out, int cap);
 

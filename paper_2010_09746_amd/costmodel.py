@@ -34,7 +34,10 @@ from . import qsim as Q
 
 from workloads import KIND_CU, KIND_CX, KIND_CZ, KIND_U, haar_u2, make_gates, phase
 
-TILE_CLASSES = ["tile_pass", "u", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch"]
+TILE_CLASSES = ["tile_pass", "u", "w", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch"]
+# compile options of calibration circuits that need them: "u" measures whole
+# 2x2 updates, so its circuit keeps every matrix whole
+CAL_OPTS = {"u": dict(full_matrices=True)}
 
 
 def _pass_ms(st: Q.State, prog: Q.Program, reps: int = 3) -> float:
@@ -64,6 +67,8 @@ def calibration_circuits(n: int, k: int, log_r: int, seed: int = 20100946 + 9) -
     c = {
         "base": [U(0)],
         "u": [U(q % R) for q in range(N + 1)],
+        # the same gates in the reduced form (all but each qubit's last)
+        "w": [U(q % R) for q in range(N + 1)],
         "u_ctrl": [U(0)] + [(KIND_CU, (q + 1) % R, q % R, haar_u2(rng)) for q in range(N)] if R > 1 else None,
         "x_reg": [U(0)] + [(KIND_CX, (q + 1) % R, q % R, None) for q in range(N)] if R > 1 else None,
         "x_lane": [U(0)] + [(KIND_CX, R + 1, q % R, None) for q in range(N)],
@@ -128,7 +133,7 @@ class CostModel:
         rows, times = [], []
         for name, g in calibration_circuits(n, k, self._log_r(k, reg_bits)).items():
             prog = Q.Program(g, n, self.dtype, form="pass", k_tile=k, max_swaps=1, pinned=self.pinned,
-                             perm_exec=self.perm_exec, reg_bits=reg_bits)
+                             perm_exec=self.perm_exec, reg_bits=reg_bits, **CAL_OPTS.get(name, {}))
             c = prog.op_counts()
             times.append(_pass_ms(st, prog))
             rows.append([c[x] for x in TILE_CLASSES])
@@ -162,6 +167,9 @@ class CostModel:
         scale = 2.0 ** (n - self.n_cal)
         tc = self.tile_costs[(k, reg_bits)]
         ms = sum(counts[c] * tc[c] for c in TILE_CLASSES)
+        # a pending phase applied on its own touches half the amplitudes of
+        # a diagonal update (rare: the W that left it ended an earlier pass)
+        ms += counts["phase"] * 0.5 * tc["diag"]
         lc = self.launch_costs
         ms += sum(counts[c] * lc[c] for c in ("plain_u", "plain_cu", "plain_cx", "plain_cz", "move",
                                                "move_fraction"))

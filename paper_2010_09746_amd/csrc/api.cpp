@@ -705,6 +705,12 @@ qs_status qs_program_op_counts(const qs_program *p, double *out, int cap)
                     case OP_NEG:
                         c[QS_OPC_NEG] += w;
                         break;
+                    case OP_W:
+                        c[QS_OPC_W] += w;
+                        break;
+                    case OP_PHASE:
+                        c[QS_OPC_PHASE] += w;
+                        break;
                     default:
                         c[QS_OPC_DIAG] += w;
                         break;

@@ -23,6 +23,8 @@
 // one a full scan of all m(n-m) candidates picks.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
+#include <complex>
 #include <cstring>
 #include <functional>
 #include <queue>
@@ -432,13 +434,137 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
     return L;
 }
 
+// ---------------------------------------------------------------------------
+// Pending one-qubit phases (lowering only; the pass is unchanged).
+//
+// Every unitary 2x2 matrix M factors as M = e^{i phi} diag(1, e^{i theta}) W
+// with W = [[a, -conj(b)], [b, a]] and a >= 0 real: with V = e^{-i phi} M in
+// SU(2), V = [[alpha, -conj(beta)], [beta, conj(alpha)]], psi = arg(alpha),
+// a = |alpha|, b = beta e^{i psi}, theta = -2 psi, and the scalar phase
+// e^{i (phi + psi)}.  W updates an amplitude pair with 12 real multiply-adds
+// instead of the 16 of a general complex 2x2.
+//
+// The lowering applies the W of each uncontrolled one-qubit gate and keeps
+// diag(1, f) pending on the gate's qubit q: the stored state equals the true
+// state up to the product of the pending phases and one scalar.  A pending
+// phase commutes with every operation that acts diagonally on q (CZ, a
+// control on q), so it stays pending through them.  The next one-qubit gate on
+// q absorbs it into its own matrix (host arithmetic, no device work); an
+// operation that acts on q non-diagonally otherwise (the target of a CNOT or
+// of a controlled gate) needs it applied first: it is folded into the W that
+// left it when that W is still in the segment being scheduled (the op becomes
+// the general 2x2 D W), else applied as a phase on the qubit.  The last
+// one-qubit gate of each qubit is applied whole, with its qubit's pending
+// phase absorbed, and the last of all also carries the accumulated scalar, so
+// the state is exact (up to rounding) when the program ends.
+struct PhaseFrame {
+    using cd = std::complex<double>;
+    bool on = false;
+    std::vector<cd> f;            // pending diag(1, f[q]) per logical qubit
+    std::vector<int64_t> w_op;    // op index of the W that left f[q], -1 if none
+    std::vector<int64_t> u_left;  // non-diagonal one-qubit gates of q not yet lowered
+    int64_t u_total = 0;          // the same over all qubits
+    cd scalar{1.0, 0.0};          // accumulated e^{i (phi + psi)}
+    int64_t seg_begin = 0;        // ops from here on belong to the segment being scheduled
+
+    void init(const qs_gate *g, const std::vector<GateInfo> &gi, int64_t ng, int n)
+    {
+        f.assign(n, cd(1.0, 0.0));
+        w_op.assign(n, -1);
+        u_left.assign(n, 0);
+        u_total = 0;
+        scalar = cd(1.0, 0.0);
+        for (int64_t v = 0; v < ng; ++v)
+            if (g[v].kind == QS_GATE_U && gi[v].act0 != ACT_Z) {
+                ++u_left[g[v].q0];
+                ++u_total;
+            }
+    }
+    static cd at(const double *m, int i) { return cd(m[2 * i], m[2 * i + 1]); }
+    static void put(double *m, int i, cd z)
+    {
+        m[2 * i] = z.real();
+        m[2 * i + 1] = z.imag();
+    }
+    static bool unitary(const cd *M)
+    {
+        const cd a = std::conj(M[0]) * M[0] + std::conj(M[2]) * M[2];
+        const cd b = std::conj(M[1]) * M[1] + std::conj(M[3]) * M[3];
+        const cd c = std::conj(M[0]) * M[1] + std::conj(M[2]) * M[3];
+        return std::abs(a - 1.0) < 1e-13 && std::abs(b - 1.0) < 1e-13 && std::abs(c) < 1e-13;
+    }
+    // Lower the uncontrolled one-qubit gate u on logical qubit q: writes the
+    // op's kind and matrix fields (OP_W: m[0] = a, m[1..2] = b; OP_U: the
+    // whole matrix) and updates the pending phase of q.
+    void one_qubit(int q, const double *u, int64_t op_index, int32_t *kind, double *m)
+    {
+        cd M[4] = {at(u, 0), at(u, 1) * f[q], at(u, 2), at(u, 3) * f[q]};
+        --u_left[q];
+        --u_total;
+        if (u_left[q] == 0 || !unitary(M)) {
+            if (u_total == 0) {
+                for (cd &x : M)
+                    x *= scalar;
+                scalar = cd(1.0, 0.0);
+            }
+            *kind = OP_U;
+            for (int i = 0; i < 4; ++i)
+                put(m, i, M[i]);
+            f[q] = cd(1.0, 0.0);
+            w_op[q] = -1;
+            return;
+        }
+        const cd det = M[0] * M[3] - M[1] * M[2];
+        const double phi = 0.5 * std::arg(det);
+        const cd alpha = M[0] * std::polar(1.0, -phi), beta = M[2] * std::polar(1.0, -phi);
+        const double a = std::abs(alpha), psi = a > 0.0 ? std::arg(alpha) : 0.0;
+        const cd b = beta * std::polar(1.0, psi);
+        *kind = OP_W;
+        std::memset(m, 0, 8 * sizeof(double));
+        m[0] = a;
+        m[1] = b.real();
+        m[2] = b.imag();
+        f[q] = std::polar(1.0, -2.0 * psi);
+        scalar *= std::polar(1.0, phi + psi);
+        scalar /= std::abs(scalar);
+        w_op[q] = op_index;
+    }
+    // Before an operation that acts on q non-diagonally other than a
+    // one-qubit gate: the pending phase must be applied.  Returns true when
+    // the caller must emit OP_PHASE with f (the W that left it is final), and
+    // writes f to *out; folds it into that W otherwise.
+    bool settle(int q, std::vector<TileOp> &ops, cd *out)
+    {
+        const cd ph = f[q];
+        const int64_t w = w_op[q];
+        f[q] = cd(1.0, 0.0);
+        w_op[q] = -1;
+        if (ph == cd(1.0, 0.0))
+            return false;
+        if (w >= seg_begin && w >= 0 && w < (int64_t)ops.size() && ops[w].kind == OP_W) {
+            TileOp &o = ops[w];
+            const double a = o.m[0];
+            const cd b(o.m[1], o.m[2]);
+            o.kind = OP_U;
+            put(o.m, 0, cd(a, 0.0));
+            put(o.m, 1, -std::conj(b));
+            put(o.m, 2, b * ph);
+            put(o.m, 3, a * ph);
+            return false;
+        }
+        *out = ph;
+        return true;
+    }
+};
+
 // Order the gates of one tile pass and insert register re-layouts.  The gates
 // may be reordered only along the commutation DAG restricted to the segment.
 constexpr int LOOKAHEAD_TARGETS = 8;
 
 int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::vector<GateInfo> &gi,
-                     int k, int log_r, std::vector<TileOp> &ops)
+                     int k, int log_r, std::vector<TileOp> &ops, PhaseFrame &pf)
 {
+    pf.seg_begin = (int64_t)ops.size();
     const int cnt = (int)lg.size();
     // in-segment predecessors
     std::vector<std::vector<int>> pred(cnt);
@@ -511,6 +637,24 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
                 op.hmask = lg[v].hmask;
                 op.hbit = lg[v].hbit;
                 std::memcpy(op.m, lg[v].m, sizeof op.m);
+                if (pf.on) {
+                    const qs_gate &src = g[lg[v].src];
+                    if (src.kind == QS_GATE_U && op.kind == OP_U) {
+                        pf.one_qubit(src.q0, src.u, (int64_t)ops.size(), &op.kind, op.m);
+                    } else if (needs_reg(v)) {
+                        // X-type target of a CNOT, or the target of a
+                        // controlled 2x2: the pending phase goes first
+                        std::complex<double> ph;
+                        if (pf.settle(src.q1, ops, &ph)) {
+                            TileOp po{};
+                            po.kind = OP_PHASE;
+                            po.slot = slot;
+                            po.m[0] = ph.real();
+                            po.m[1] = ph.imag();
+                            ops.push_back(po);
+                        }
+                    }
+                }
                 ops.push_back(op);
                 emitted[v] = 1;
                 --left;
@@ -730,12 +874,44 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
     p.ops.clear();
     std::vector<int> sphys = p.sigma0;
 
+    PhaseFrame pf;
     auto plain = [&](int64_t v) {
         Launch L;
         L.type = L_PLAIN;
         L.gate = g[v];
         L.gate.q0 = sphys[g[v].q0];
         L.gate.q1 = g[v].kind == QS_GATE_U ? -1 : sphys[g[v].q1];
+        if (pf.on) {
+            if (g[v].kind == QS_GATE_U && gi[v].act0 != ACT_Z) {
+                // one launch of the whole matrix with the pending phase absorbed
+                int32_t kind = OP_U;
+                double m[8];
+                const int64_t left = pf.u_left[g[v].q0];
+                pf.u_left[g[v].q0] = 1;  // forces the whole-matrix form
+                pf.one_qubit(g[v].q0, g[v].u, -1, &kind, m);
+                pf.u_left[g[v].q0] = left - 1;
+                std::memcpy(L.gate.u, m, sizeof m);
+            } else if ((g[v].kind == QS_GATE_CX || g[v].kind == QS_GATE_CU) && gi[v].act1 != ACT_Z) {
+                std::complex<double> ph;
+                std::vector<TileOp> none;
+                const int64_t sb = pf.seg_begin;
+                pf.seg_begin = 0;  // no fusible op here: a launch of its own
+                if (pf.settle(g[v].q1, none, &ph)) {
+                    Launch D;
+                    D.type = L_PLAIN;
+                    D.gate = qs_gate{};
+                    D.gate.kind = QS_GATE_U;
+                    D.gate.q0 = sphys[g[v].q1];
+                    D.gate.q1 = -1;
+                    D.gate.u[0] = 1.0;
+                    D.gate.u[6] = ph.real();
+                    D.gate.u[7] = ph.imag();
+                    p.launches.push_back(D);
+                    ++p.stats.n_plain;
+                }
+                pf.seg_begin = sb;
+            }
+        }
         p.launches.push_back(L);
         ++p.stats.n_plain;
     };
@@ -766,6 +942,10 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
             tile_shape(k, dt, o.reg_bits, &log_r, &log_nt);
         std::vector<int> spass = p.sigma0;
         size_t i = 0;
+        // reduced one-qubit updates only where tile passes run them
+        pf.on = tiled && (o.flags & QS_OPT_FULL_MATRICES) == 0;
+        if (pf.on)
+            pf.init(g, gi, ng, n);
         // Lower the instructions from i on.  A run of ApplyGate instructions is
         // a complete segment once an instruction of another kind follows it
         // (or, with final, at the end).
@@ -830,7 +1010,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                     L.log_nt = log_nt;
                     L.pos = pos;
                     L.op_begin = (int)p.ops.size();
-                    p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops);
+                    p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops, pf);
                     L.op_count = (int)p.ops.size() - L.op_begin;
                     set_direct_io(L, p.ops, dt);
                     p.launches.push_back(L);

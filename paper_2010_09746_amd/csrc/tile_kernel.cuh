@@ -162,6 +162,95 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
         }
     }
 
+    // W = [[a, -conj(b)], [b, a]] (a real) on one pair, in place: 12 real
+    // multiply-adds.  x' = a x - conj(b) y and y' = b x + a y; the partial
+    // sums read only the other element of the pair, and each output's last
+    // multiply-add reads its own register.  In FP64 the sequence is written
+    // out as instructions: compiled from the expressions, the register
+    // allocator kept the old values of whole pairs alive and the tile kernel
+    // needed 149 VGPRs (3 wavefronts per SIMD) instead of 117 (4).
+    static __device__ __forceinline__ void wpair(C &x, C &y, R a, R br, R bi)
+    {
+        if constexpr (sizeof(R) == 8) {
+            double p0, p1, p2, p3;
+            __asm__("v_mul_f64 %[p0], %[yi], -%[bi]\n\t"
+                    "v_mul_f64 %[p1], %[yr], %[bi]\n\t"
+                    "v_mul_f64 %[p2], %[xi], -%[bi]\n\t"
+                    "v_mul_f64 %[p3], %[xr], %[bi]\n\t"
+                    "v_fma_f64 %[p0], -%[br], %[yr], %[p0]\n\t"
+                    "v_fma_f64 %[p1], -%[br], %[yi], %[p1]\n\t"
+                    "v_fma_f64 %[p2], %[br], %[xr], %[p2]\n\t"
+                    "v_fma_f64 %[p3], %[br], %[xi], %[p3]\n\t"
+                    "v_fma_f64 %[xr], %[a], %[xr], %[p0]\n\t"
+                    "v_fma_f64 %[xi], %[a], %[xi], %[p1]\n\t"
+                    "v_fma_f64 %[yr], %[a], %[yr], %[p2]\n\t"
+                    "v_fma_f64 %[yi], %[a], %[yi], %[p3]"
+                    : [xr] "+v"(x.x), [xi] "+v"(x.y), [yr] "+v"(y.x), [yi] "+v"(y.y), [p0] "=&v"(p0),
+                      [p1] "=&v"(p1), [p2] "=&v"(p2), [p3] "=&v"(p3)
+                    : [a] "s"(a), [br] "s"(br), [bi] "s"(bi));
+            return;
+        }
+        R p0 = -bi * y.y, p1 = bi * y.x, p2 = -bi * x.y, p3 = bi * x.x;
+        p0 = fmadd(-br, y.x, p0);
+        p1 = fmadd(-br, y.y, p1);
+        p2 = fmadd(br, x.x, p2);
+        p3 = fmadd(br, x.y, p3);
+        x.x = fmadd(a, x.x, p0);
+        x.y = fmadd(a, x.y, p1);
+        y.x = fmadd(a, y.x, p2);
+        y.y = fmadd(a, y.y, p3);
+    }
+    // W on slot S, every pair.  With SW the slot's pattern bit is flipped.
+    template <int S, bool SW> static __device__ __forceinline__ void wfly(C (&v)[NR], R a, R br, R bi)
+    {
+#pragma unroll
+        for (int jj = 0; jj < NR / 2; ++jj) {
+            const int j = pair_lo<S>(jj), j1 = j | (1 << S);
+            if (SW)
+                wpair(v[j1], v[j], a, br, bi);
+            else
+                wpair(v[j], v[j1], a, br, bi);
+        }
+    }
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_w(int slot, uint32_t sw, C (&v)[NR], R a, R br, R bi)
+    {
+        if (slot == S || S == LOG_R - 1) {
+            if (sw)
+                wfly<S, true>(v, a, br, bi);
+            else
+                wfly<S, false>(v, a, br, bi);
+        } else if constexpr (S + 1 < LOG_R) {
+            dispatch_w<S + 1>(slot, sw, v, a, br, bi);
+        }
+    }
+
+    // multiply by (pr, pi) the amplitudes whose pattern bit of slot S is 1
+    // (the slot bit itself with SW clear, its complement with SW set)
+    template <int S, bool SW> static __device__ __forceinline__ void phase_slots(C (&v)[NR], R pr, R pi)
+    {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (((j >> S) & 1) != (SW ? 1 : 0)) {
+                const R x = v[j].x;
+                v[j].x = fmadd(pr, x, -pi * v[j].y);
+                v[j].y = fmadd(pr, v[j].y, pi * x);
+            }
+        }
+    }
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_phase(int slot, uint32_t sw, C (&v)[NR], R pr, R pi)
+    {
+        if (slot == S || S == LOG_R - 1) {
+            if (sw)
+                phase_slots<S, true>(v, pr, pi);
+            else
+                phase_slots<S, false>(v, pr, pi);
+        } else if constexpr (S + 1 < LOG_R) {
+            dispatch_phase<S + 1>(slot, sw, v, pr, pi);
+        }
+    }
+
     // flip the sign bit where sg has it set (sg is 0 or the sign mask)
     static __device__ __forceinline__ R flip_sign(R x, uint32_t sg)
     {
@@ -459,7 +548,11 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
                     const uint32_t rv = rm & ~fl;
                     const bool lp = (tbase & lm) == lm;
                     const int slot = cur.slot;
-                    if (kind == OP_U) {
+                    if (kind == OP_W) {
+                        dispatch_w(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1], (R)cur.m[2]);
+                    } else if (kind == OP_PHASE) {
+                        dispatch_phase(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1]);
+                    } else if (kind == OP_U) {
                         Mat<R> m;
 #pragma unroll
                         for (int q = 0; q < 8; ++q)

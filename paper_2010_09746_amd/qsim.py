@@ -60,7 +60,7 @@ class QsimError(RuntimeError):
 class qs_run_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("k_tile", ctypes.c_int32), ("max_swaps", ctypes.c_int32),
                 ("pinned", ctypes.c_int32), ("perm_exec", ctypes.c_int32), ("max_fuse", ctypes.c_int32),
-                ("reg_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("reg_bits", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class qs_program_stats(ctypes.Structure):
@@ -184,8 +184,11 @@ def _ints(x) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(x, dtype=np.intc))
 
 
+QS_OPT_FULL_MATRICES = 1
+
+
 def make_opts(form="pass", k_tile=12, max_swaps=1, pinned=0, perm_exec="move", max_fuse=0,
-              reg_bits=0) -> qs_run_opts:
+              reg_bits=0, full_matrices=False) -> qs_run_opts:
     o = qs_run_opts()
     o.form = {"plain": QS_FORM_PLAIN, "pass": QS_FORM_PASS}.get(form, form)
     o.k_tile = k_tile
@@ -194,6 +197,7 @@ def make_opts(form="pass", k_tile=12, max_swaps=1, pinned=0, perm_exec="move", m
     o.perm_exec = {"move": QS_PERM_MOVE, "relabel": QS_PERM_RELABEL}.get(perm_exec, perm_exec)
     o.max_fuse = max_fuse
     o.reg_bits = reg_bits
+    o.flags = QS_OPT_FULL_MATRICES if full_matrices else 0
     return o
 
 
@@ -270,7 +274,7 @@ def qs_program_get_stats(h: int) -> dict:
 
 
 OPC_NAMES = ["tile_pass", "u", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch", "plain_u",
-             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction"]
+             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction", "w", "phase"]
 
 
 def qs_program_op_counts(h: int) -> dict:
