@@ -58,6 +58,15 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many GiB 3 times (a plain copy kernel of "
                          "known size, used to scale hardware byte counters)")
+    ap.add_argument("--forms", default="precision,batch,serve",
+                    help="forms timed after the headline and reported as sub-objects of its line (comma-separated "
+                         "subset of precision, batch, serve; empty: none)")
+    ap.add_argument("--form-steps", type=int, default=1, help="timed steps of each form after its warm-up")
+    ap.add_argument("--retune", action="store_true", help="batch: ignore the autotuner's cache")
+    ap.add_argument("--accuracy-requests", type=int, default=64,
+                    help="serve: requests re-run alone in complex128 to state the served accuracy")
+    ap.add_argument("--cpu-one-core-seconds", type=float, default=4.0,
+                    help="oracle sample length with one thread (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--rate-sweep", default="",
@@ -91,12 +100,27 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(gates, n, seconds, threads=0):
-    """The oracle (plain C, complex128, OpenMP) on this host: gates of the
-    same circuit applied one by one until ``seconds`` have elapsed, with
-    ``threads`` OpenMP threads (0: the OpenMP default)."""
-    import numpy as np
+def cpu_model():
+    """CPU model name of this host and the number of CPUs this process may use."""
+    name = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return dict(model=name, cpus_available=avail, cpus_total=os.cpu_count())
 
+
+def _oracle_rate(gates, n, seconds, threads):
+    """Apply the gates one by one with the oracle until `seconds` have passed
+    (or the circuit ends); returns (gates done, seconds, threads used)."""
     import oracle as O
 
     O.lib()
@@ -107,19 +131,47 @@ def cpu_baseline(gates, n, seconds, threads=0):
     t0 = time.perf_counter()
     while done < len(gates) and time.perf_counter() - t0 < seconds:
         g = gates[done]
-        q1 = int(g["q1"])
-        O.apply_gate(s, n, int(g["kind"]), int(g["q0"]), q1, g["u"])
+        O.apply_gate(s, n, int(g["kind"]), int(g["q0"]), int(g["q1"]), g["u"])
         done += 1
     dt = time.perf_counter() - t0
+    used = O.threads()
     del s
-    return dict(value=done * float(1 << n) / dt, unit="amplitude-updates/s", cores=O.threads(), kind="oracle",
-                sample=f"first {done} gates of the same {n}-qubit circuit, complex128, {dt:.1f} s")
+    return done, dt, used
 
 
-def precision(a):
+def cpu_baseline(gates, n, seconds, threads=0, one_core_seconds=0.0):
+    """The oracle (plain C, complex128, OpenMP) on this host: gates of the
+    same circuit applied one by one until ``seconds`` have elapsed, with
+    ``threads`` OpenMP threads (0: the OpenMP default), then the same with one
+    thread, the 16-qubit plain workload in full and the 32-qubit precision
+    workload's circuit at 28 qubits (a sample)."""
+    import oracle as O
+    from workloads import config_circuit
+
+    default_threads = O.threads()
+    done, dt, used = _oracle_rate(gates, n, seconds, threads)
+    out = dict(value=done * float(1 << n) / dt, unit="amplitude-updates/s", cores=used, kind="oracle",
+               sample=f"first {done} gates of the same {n}-qubit circuit, complex128, {dt:.1f} s, {used} threads",
+               host=cpu_model())
+    if one_core_seconds > 0:
+        d1, t1, _ = _oracle_rate(gates, n, one_core_seconds, 1)
+        out["one_core"] = dict(value=d1 * float(1 << n) / t1, sample=f"first {d1} gates, {t1:.1f} s, 1 thread")
+    O.set_threads(threads if threads > 0 else default_threads)
+    g1 = config_circuit(1)
+    d, t, u = _oracle_rate(g1, 16, 60.0, threads)
+    out["plain_16q"] = dict(value=d * float(1 << 16) / t, seconds=t, gates=d, threads=u,
+                            workload="16 qubits, 20 layers, CNOT only, in full")
+    g3 = config_circuit(3, n=28)
+    d, t, u = _oracle_rate(g3, 28, max(1.0, seconds / 3), threads)
+    out["precision_28q"] = dict(value=d * float(1 << 28) / t, seconds=t, gates=d, threads=u,
+                                workload="the precision workload's layered circuit at 28 qubits, first gates")
+    return out
+
+
+def precision_form(a):
     """32 qubits, 50 layers: the pass form in complex64 and in complex128 on
     the same circuit; per-result error of complex64 against complex128 (FP64
-    read-out on both)."""
+    read-out on both).  Returns the form's sub-object."""
     import numpy as np
     import torch
 
@@ -133,6 +185,7 @@ def precision(a):
     upd = len(gates) * float(1 << n)
     out = {}
     states = {}
+    steps = max(1, a.form_steps)
     for dt, k in (("c64", a.k), ("c128", a.k)):
         st = Q.State(n, dt)
         pin = a.pinned_c64 if (dt == "c64" and a.pinned_c64 is not None) else a.pinned
@@ -140,7 +193,7 @@ def precision(a):
         st.run(gates, **opts)  # warm-up
         torch.cuda.synchronize()
         ts = []
-        for _ in range(max(1, a.steps)):
+        for _ in range(steps):
             t0 = time.perf_counter()
             st.set_basis(0)
             st.run(gates, **opts)
@@ -149,32 +202,44 @@ def precision(a):
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         ms = float(np.median(ts))
-        out[dt] = dict(ms_per_step=ms * 1e3, value=upd / ms, k_tile=k, pinned=pin, max_swaps=a.r, norm=st.norm())
+        out[dt] = dict(ms_per_step=ms * 1e3, value=upd / ms, unit="amplitude-updates/s", k_tile=k, pinned=pin,
+                       max_swaps=a.r, norm=st.norm())
         states[dt] = (st, z, amp)
-        print(f"{dt}: {ms * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        print(f"precision {dt}: {ms * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
     loss, mx = states["c64"][0].fidelity(states["c128"][0])
     err = dict(fidelity_loss=loss, max_abs_amp=mx,
                max_abs_expect_z=float(np.abs(states["c64"][1] - states["c128"][1]).max()),
                max_abs_sampled_amp=float(np.abs(states["c64"][2] - states["c128"][2]).max()),
                norm_c64_minus_1=states["c64"][0].norm() - 1.0, norm_c128_minus_1=states["c128"][0].norm() - 1.0)
+    for st, _, _ in states.values():
+        st.close()
+    states.clear()
+    torch.cuda.empty_cache()
+    return {"workload": f"random circuit n={n}, {layers} layers ({len(gates)} gates), complex64 bulk with FP64 "
+                        f"read-out against complex128 (the complex128 path is checked against the oracle at 28 "
+                        f"qubits by the GPU tests)",
+            "steps": steps, "c64": out["c64"], "c128": out["c128"], "c64_vs_c128": err,
+            "tolerance": {"fidelity_loss": 1e-6, "max_abs_amp": 1e-5},
+            "within_tolerance": bool(loss <= 1e-6 and mx <= 1e-5)}
+
+
+def precision(a):
+    r = precision_form(a)
     line = {
-        "metric": "amplitude-updates/s", "value": out["c64"]["value"], "unit": "amplitude-updates/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": 1, "ms_per_step": out["c64"]["ms_per_step"], "higher_is_better": True,
+        "metric": "amplitude-updates/s", "value": r["c64"]["value"], "unit": "amplitude-updates/s", "n_gpus": 1,
+        "steps": r["steps"], "warmup": 1, "ms_per_step": r["c64"]["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"precision form: random circuit n={n}, {layers} layers ({len(gates)} gates), complex64 "
-                               f"bulk with FP64 read-out vs complex128", "parallelism": "1 GPU"},
-        "c64": out["c64"], "c128": out["c128"], "c64_vs_c128": err,
-        "tolerance": {"fidelity_loss": 1e-6, "max_abs_amp": 1e-5},
-        "within_tolerance": bool(loss <= 1e-6 and mx <= 1e-5),
+        "config": {"workload": "precision form: " + r["workload"], "parallelism": "1 GPU"},
     }
+    line.update({k: v for k, v in r.items() if k not in ("workload", "steps")})
     print(json.dumps(line), flush=True)
 
 
-def batch(a):
+def batch_form(a):
     """256 seeded circuits, n uniform in [10, 24], depth uniform in [10, 60],
-    complex64: one launch per pass level over all circuits, the whole run
-    replayed from a HIP graph, with k and the fusion depth chosen by the
-    autotuner.  Accuracy against the oracle is covered by the GPU tests."""
+    complex64, with the autotuner's choice; tuning time reported apart from
+    the replay time.  Accuracy against the oracle is covered by the GPU
+    tests.  Returns the form's sub-object."""
     import numpy as np
 
     from paper_2010_09746_amd import autotune, qsim as Q
@@ -183,44 +248,51 @@ def batch(a):
     wl = batch_workload(count=256)
     circuits = [(n, g) for n, d, g in wl]
     t0 = time.perf_counter()
-    best, table = autotune.tune_batch(circuits, "c64", reps=2,
+    best, table = autotune.tune_batch(circuits, "c64", reps=2, refresh=a.retune,
                                       log=lambda m: print("tune " + m, file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
+    t1 = time.perf_counter()
     b = Q.Batch(circuits, "c64", **best)
+    build_s = time.perf_counter() - t1
     b.run()
     b.results()
     ts = []
-    for _ in range(max(1, a.steps)):
-        t1 = time.perf_counter()
+    for _ in range(max(1, a.form_steps)):
+        t2 = time.perf_counter()
         b.run()
         z, nrm = b.results()
-        ts.append(time.perf_counter() - t1)
+        ts.append(time.perf_counter() - t2)
     sec = float(np.median(ts))
     st = b.stats()
     upd = sum(len(g) * float(1 << n) for n, g in circuits)
     b.close()
+    print(f"batch: {sec * 1e3:.1f} ms per replay", file=sys.stderr, flush=True)
+    return {"workload": "256 seeded layered circuits, n uniform in [10,24], depth uniform in [10,60], complex64; "
+                        "output <Z_0> and norm per circuit",
+            "value": upd / sec, "unit": "amplitude-updates/s", "ms_per_replay": sec * 1e3,
+            "circuits_per_s": len(circuits) / sec, "replays": len(ts),
+            "tuned": best, "tune_seconds": tune_s, "tune_candidates": len(table), "build_seconds": build_s,
+            "batch_stats": st, "max_norm_error": float(np.abs(nrm - 1).max())}
+
+
+def batch(a):
+    r = batch_form(a)
     line = {
-        "metric": "amplitude-updates/s", "value": upd / sec, "unit": "amplitude-updates/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batching form: 256 seeded layered circuits, n uniform in [10,24], depth uniform in "
-                               "[10,60], complex64; per pass level one shared persistent launch (large passes as "
-                               "tile-pass launches of their own), the sequence under a HIP graph; output <Z_0> and "
-                               "norm per circuit", "parallelism": "1 GPU"},
-        "circuits_per_s": len(circuits) / sec,
-        "tuned": best, "tune_seconds": tune_s, "tune_candidates": len(table),
-        "batch_stats": st,
-        "max_norm_error": float(np.abs(nrm - 1).max()),
+        "metric": "amplitude-updates/s", "value": r["value"], "unit": "amplitude-updates/s", "n_gpus": 1,
+        "steps": r["replays"], "warmup": 1, "ms_per_step": r["ms_per_replay"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batching form: " + r["workload"], "parallelism": "1 GPU"},
     }
+    line.update({k: v for k, v in r.items() if k not in ("workload", "value", "unit")})
     print(json.dumps(line), flush=True)
 
 
-def serve(a):
+def serve_form(a):
     """Seeded Poisson trace (rate, count), n uniform in [12, 30], depth uniform
     in [20, 100], complex64 with FP64 reductions, 200 GB budget, states
     resident; each request returns <Z_q> for all q and 16 sampled amplitudes.
-    Accuracy against the oracle is covered by the GPU tests; here the norm of
-    every served state is reported."""
+    The accuracy the latencies are quoted at is measured against complex128
+    runs of the same circuits.  Returns the form's sub-object."""
     import numpy as np
 
     from paper_2010_09746_amd.serving import Server, latency_summary
@@ -237,33 +309,37 @@ def serve(a):
     st = latency_summary(rec)
     nerr = [abs(res[r["id"]]["norm"] - 1.0) for r in reqs]
     main_stats = dict(srv.last_stats)
-    accuracy = served_accuracy(reqs, res, a.serve_k)
     sweep = []
     for rate in [float(x) for x in a.rate_sweep.split(",") if x.strip()]:
         tr = request_trace(count=a.sweep_requests, rate=rate)
         rq = [dict(r, gates=layered_circuit(r["n"], r["depth"], r["seed"])) for r in tr]
         _, rc = srv.serve(rq, realtime=True)
         sweep.append(dict(rate=rate, **latency_summary(rc)))
-    line = {
-        "metric": "served p50/p99 latency", "value": st["p99_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": st["makespan_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"serving form: Poisson trace {a.requests} requests at {a.rate}/s, n uniform in "
-                               f"[12,30], depth uniform in [20,100], complex64 with FP64 reductions, 200 GB budget, "
-                               f"<Z_q> all q + 16 sampled amplitudes per request; tile qubits {a.serve_k}, "
-                               f"{a.serve_wg} workgroups per CU; passes of at least "
-                               f"{a.serve_solo_tiles if a.serve_solo_tiles is not None else 2 ** 10} tiles "
-                               f"as launches of their own (0: none)",
-                   "parallelism": "1 GPU"},
-        "latency": st, "server": main_stats,
-        "max_norm_error": float(np.max(nerr)), "accuracy": accuracy,
-        "rate_sweep": sweep,
-    }
     srv.close()
+    accuracy = served_accuracy(reqs, res, a.serve_k, count=a.accuracy_requests)
+    print(f"serve: p50 {st['p50_s']:.2f} s, p99 {st['p99_s']:.2f} s, {st['throughput_req_s']:.1f} requests/s",
+          file=sys.stderr, flush=True)
+    return {"workload": f"Poisson trace of {a.requests} requests at {a.rate}/s, n uniform in [12,30], depth "
+                        f"uniform in [20,100], complex64 with FP64 reductions, 200 GB budget, <Z_q> all q + 16 "
+                        f"sampled amplitudes per request; tile qubits {a.serve_k}",
+            "p50_s": st["p50_s"], "p99_s": st["p99_s"], "throughput_req_s": st["throughput_req_s"],
+            "latency": st, "server": main_stats, "max_norm_error": float(np.max(nerr)), "accuracy": accuracy,
+            "rate_sweep": sweep}
+
+
+def serve(a):
+    r = serve_form(a)
+    line = {
+        "metric": "served p50/p99 latency", "value": r["p99_s"], "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": r["latency"]["makespan_s"] * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving form: " + r["workload"], "parallelism": "1 GPU"},
+    }
+    line.update({k: v for k, v in r.items() if k != "workload"})
     print(json.dumps(line), flush=True)
 
 
-def served_accuracy(reqs, res, k, count=8):
+def served_accuracy(reqs, res, k, count=64):
     """Error of the served complex64 results against complex128 runs of the
     same circuits (pass form, one at a time), on `count` requests spread over
     the trace: max |d<Z_q>| over all q and max |d amp| over the sampled
@@ -489,13 +565,28 @@ def main():
         roofline = dict(main, traffic=traffic, kernel="k_tile", avg_ms=tile["avg_ms"],
                         launches_per_step=tile["launches"] / a.steps, other_ceiling=other)
 
+    torch.cuda.synchronize()
+    st.close()
+    del st
+    torch.cuda.empty_cache()
     cpu = None
     if a.cpu_seconds > 0:
-        torch.cuda.synchronize()
-        st.close()
-        del st
+        cpu = cpu_baseline(gates, n, a.cpu_seconds, a.cpu_threads, a.cpu_one_core_seconds)
+
+    # the other forms of the metric, each timed after the headline
+    forms = {}
+    runners = {"precision": precision_form, "batch": batch_form, "serve": serve_form}
+    for name in [x.strip() for x in a.forms.split(",") if x.strip()]:
+        if name not in runners:
+            forms[name] = {"error": "unknown form"}
+            continue
+        t0 = time.perf_counter()
+        try:
+            forms[name] = runners[name](a)
+        except Exception as e:  # reported in the line; the headline stands
+            forms[name] = {"error": f"{type(e).__name__}: {e}"}
+        forms[name]["wall_seconds"] = time.perf_counter() - t0
         torch.cuda.empty_cache()
-        cpu = cpu_baseline(gates, n, a.cpu_seconds, a.cpu_threads)
 
     value = amp_updates / ms_pass
     line = {
@@ -526,6 +617,7 @@ def main():
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "device": dev,
     }
     print(json.dumps(line), flush=True)

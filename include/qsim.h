@@ -277,15 +277,26 @@ qs_status qs_synchronize(qs_state *s);
 
 /* ---- batching form ---------------------------------------------------------- */
 
-/* Options of a batch.
- *   k_tile     tile qubits, shared by every circuit (7 <= k_tile <= every n)
+/* Options of a batch (and of a server, which uses k_tile, max_swaps, pinned,
+ * reg_bits, max_fuse, wg_per_cu and chunk).
+ *   k_tile     batch: largest tile; circuit c uses 2^k amplitudes per tile
+ *              with k = min(n_c, k_tile) (a circuit of at most k_tile qubits
+ *              is one tile: its whole state in one workgroup, all its gates in
+ *              one pass), 9 <= k_tile <= 12, every n_c >= 9.  Server: the
+ *              tile size of every request (7 <= k_tile <= every n).
  *   max_swaps  r of the pass (see qs_run_opts); placements are relabelled
  *   pinned     positions never exchanged out (see qs_run_opts)
- *   reg_bits   amplitudes per thread = 2^reg_bits (0 = library choice)
+ *   reg_bits   server: amplitudes per thread = 2^reg_bits (0 = library
+ *              choice).  Batch: ignored (256 threads per tile,
+ *              2^(k - 8) amplitudes each)
  *   max_fuse   gates per tile pass bound (0 = none)
- *   wg_per_cu  workgroups per compute unit of each level launch
- *   chunk      tiles per work item
- *   use_graph  1: capture the launch sequence once in a HIP graph and replay it */
+ *   wg_per_cu  workgroups per compute unit of the persistent launch (0 = 4)
+ *   chunk      tiles per work item (0 = 1)
+ *   use_graph  batch: 1 = capture the run once in a HIP graph and replay it
+ *   wait_ms    batch: a work item gives up waiting for its circuit's previous
+ *              pass after this long (0 = 2000); the run then reports
+ *              QS_ERR_HIP.  -1: every wait gives up at once (a test of that
+ *              path: the launch still drains and the run reports the error) */
 typedef struct {
     int32_t k_tile;
     int32_t max_swaps;
@@ -295,6 +306,8 @@ typedef struct {
     int32_t wg_per_cu;
     int32_t chunk;
     int32_t use_graph;
+    int32_t wait_ms;
+    int32_t reserved;
 } qs_batch_opts;
 
 typedef struct {
@@ -303,36 +316,52 @@ typedef struct {
 } qs_batch_stats;
 
 /* Compile count circuits (circuit c: n_qubits[c] qubits, gates[c] a host array
- * of n_gates[c] gates) for execution together.  Circuits advance one pass
- * level at a time: level L holds every circuit's L-th tile pass, and one
- * persistent launch strides over the tiles of a level (large passes run as
- * launches of their own; see qs_batch_set_solo_tiles).  The library allocates
- * one device buffer holding every state (complex64 or complex128), the
- * compiled pass tables and its own HIP stream.  Compilation runs on host
+ * of n_gates[c] gates) for execution together.  Each circuit is compiled with
+ * its own tile size (see qs_batch_opts.k_tile) and its tile passes become work
+ * items (chunk tiles each).  A run is one persistent launch: workgroups take
+ * items in a fixed order by ticket, and an item whose circuit's previous pass
+ * is not complete waits for it (the order puts every pass's items after all
+ * items of the pass before it, which guarantees progress).  The first pass of
+ * each circuit starts from |0...0> without reading the state; the workgroup
+ * that completes a circuit's last pass reduces its read-out.  The library
+ * allocates one device buffer holding every state (complex64 or complex128),
+ * the compiled tables and its own HIP stream.  Compilation runs on host
  * threads. */
 qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *gates, const int64_t *n_gates,
                           qs_dtype dt, const qs_batch_opts *opts, qs_batch **out);
-/* Enqueue one execution: every state set to |0...0>, one persistent launch per
- * pass level (followed by the launches of that level's large passes), then
- * the per-circuit read-out.  With use_graph the whole sequence is captured in
- * a HIP graph on the first call and replayed after. */
+/* Enqueue one run: a small kernel that clears the run's counters, then the
+ * persistent launch.  With use_graph both are captured in a HIP graph on the
+ * first call and replayed after. */
 qs_status qs_batch_run(qs_batch *b);
-/* Passes with at least min_tiles tiles (2^(n - k_tile)), other than each
- * circuit's last, run as tile-pass launches of their own (one workgroup per
- * tile) after their level's launch; 0: every pass in the level launches.
- * Default 2^12 tiles.  Waits for the last run; the next qs_batch_run captures
- * the new launch sequence.  Results do not depend on it.  QS_ERR_ARG for
- * min_tiles < 0. */
-qs_status qs_batch_set_solo_tiles(qs_batch *b, int64_t min_tiles);
 /* Wait for the last run; z0[c] = <Z_0> and norms[c] = sum |a|^2 of circuit c
- * (host arrays of count doubles, FP64 accumulation; either may be NULL). */
+ * (host arrays of count doubles, FP64 accumulation; either may be NULL).  The
+ * wait is bounded: a run that has not finished after 60 s plus four times
+ * wait_ms gets its waits aborted from the host and QS_ERR_HIP is returned, as
+ * it is when a work item gave up waiting. */
 qs_status qs_batch_results(qs_batch *b, double *z0, double *norms);
 /* Amplitudes of one circuit (n <= 26) in logical order into out (host,
- * 2^(n+1) doubles); call after qs_batch_results. */
+ * 2^(n+1) doubles); waits for the last run as qs_batch_results does. */
 qs_status qs_batch_read_state(qs_batch *b, int circuit, double *out);
 qs_status qs_batch_get_stats(const qs_batch *b, qs_batch_stats *out);
 qs_status qs_batch_synchronize(qs_batch *b);
 qs_status qs_batch_destroy(qs_batch *b);
+
+/* The host-side plan of a batch, without a device: the pass table (circuit by
+ * circuit) and the work items in ticket order, as qs_batch_create builds
+ * them.  Item i covers tiles [t0, t1) of pass `pass` and may start once pass
+ * `dep` (-1: none) has completed `need` tiles.  Writes up to pass_cap and
+ * item_cap records (host arrays) and the full counts. */
+typedef struct {
+    int32_t circuit, level, k_tile, last;
+    int64_t tiles;
+} qs_batch_pass_info;
+typedef struct {
+    int32_t pass, dep;
+    int64_t t0, t1, need;
+} qs_batch_item_info;
+qs_status qs_batch_plan(int count, const int *n_qubits, const qs_gate *const *gates, const int64_t *n_gates,
+                        qs_dtype dt, const qs_batch_opts *opts, qs_batch_pass_info *passes, int64_t pass_cap,
+                        int64_t *n_passes, qs_batch_item_info *items, int64_t item_cap, int64_t *n_items);
 
 /* ---- serving form ------------------------------------------------------------ */
 

@@ -1,9 +1,9 @@
 """Autotuner for the batching form.
 
-Chooses the tile size k, the exchanges per permutation r (which sets the
-fusion depth: gates per tile pass), the register bits per thread, the
-persistent launch shape, the pinned positions and which large passes run as
-launches of their own, by timing graph replays of the actual batch on the
+Chooses the largest tile size k (each circuit uses min(n, k)), the
+exchanges per permutation r (which sets the fusion depth: gates per tile
+pass), the persistent launch shape (workgroups per CU, tiles per work item)
+and the pinned positions, by timing graph replays of the actual batch on the
 device.  Results are cached in JSON keyed by device name, amplitude type and a
 signature of the workload (qubit-count histogram and gate count).
 """
@@ -66,68 +66,52 @@ def _time(circuits, dtype, opts, reps):
 
 
 def candidates(n_min: int, dtype):
-    """Tile shapes instantiated for the batching form (64 or 128 threads)."""
-    ks = [k for k in (8, 9, 10) if k <= n_min]
-    regs = {8: [2], 9: [2, 3], 10: [3, 4]}
-    for k in ks:
-        for rb in regs[k]:
-            for r in (2, 4, 8, 16):
-                yield dict(k_tile=k, reg_bits=rb, max_swaps=r)
+    """Largest tile k (circuits of at most k qubits run as one tile) and the
+    exchange bundle r, which sets the fusion depth (gates per pass)."""
+    for k in (10, 11, 12):
+        for r in (4, 8, 16):
+            yield dict(k_tile=k, max_swaps=r)
 
 
 def tune_batch(circuits, dtype="c64", cache_path=DEFAULT_CACHE, reps=2, refresh=False, log=None):
     """Returns (best options dict, table of (options, seconds)).  Stage 1
-    searches k, register bits and r with a default launch shape; stage 2
-    searches the launch shape (workgroups per CU, tiles per item) for the
-    best stage-1 choice."""
+    searches the largest tile k and r with a default launch shape; stage 2
+    the launch shape (workgroups per CU, tiles per work item); stage 3 the
+    pinned positions."""
     dev = Q.qs_device_info()["name"]
-    key = f"{dev}|{dtype}|{signature(circuits, dtype)}"
+    key = f"{dev}|{dtype}|queue|{signature(circuits, dtype)}"
     cache = _load(cache_path)
     if not refresh and key in cache:
         return cache[key]["best"], cache[key]["table"]
     n_min = min(int(n) for n, _ in circuits)
     table = []
-    base = dict(pinned=3, wg_per_cu=8, chunk=8, use_graph=1)
-    for c in candidates(n_min, dtype):
-        o = dict(base, **c)
+
+    def trial(o):
         try:
             t, _ = _time(circuits, dtype, o, reps)
         except Q.QsimError as e:
             if log:
                 log(f"skip {o}: {e}")
-            continue
+            return
         table.append((o, t))
         if log:
             log(f"{o} -> {t * 1e3:.2f} ms")
+
+    base = dict(pinned=3 if Q.elem_bytes(dtype) == 16 else 4, wg_per_cu=4, chunk=4, use_graph=1)
+    for c in candidates(n_min, dtype):
+        trial(dict(base, **c))
     best = min(table, key=lambda x: x[1])[0]
-    for wg in (4, 8, 16):
-        for ch in (2, 8, 32):
+    for wg in (3, 4, 5):
+        for ch in (1, 2, 4, 8):
             o = dict(best, wg_per_cu=wg, chunk=ch)
-            if o == best:
-                continue
-            t, _ = _time(circuits, dtype, o, reps)
-            table.append((o, t))
-            if log:
-                log(f"{o} -> {t * 1e3:.2f} ms")
+            if o != best:
+                trial(o)
     best = min(table, key=lambda x: x[1])[0]
-    # stage 3: pinned positions (a 128-byte line is 8 complex128 or 16
-    # complex64 amplitudes: 3 or 4 positions), then which passes run as
-    # launches of their own (tiles threshold)
+    # a 128-byte line is 8 complex128 or 16 complex64 amplitudes
     for pin in (3, 4):
         o = dict(best, pinned=pin)
-        if o == best or (pin == 4 and Q.elem_bytes(dtype) != 8):
-            continue
-        t, _ = _time(circuits, dtype, o, reps)
-        table.append((o, t))
-        if log:
-            log(f"{o} -> {t * 1e3:.2f} ms")
-    best = min(table, key=lambda x: x[1])[0]
-    for solo in (0, 1 << 10, 1 << 12, 1 << 14):
-        o = dict(best, solo_tiles=solo)
-        t, _ = _time(circuits, dtype, o, reps)
-        table.append((o, t))
-        if log:
-            log(f"{o} -> {t * 1e3:.2f} ms")
+        if o != best:
+            trial(o)
     best = min(table, key=lambda x: x[1])[0]
     cache[key] = dict(best=best, table=table)
     _save(cache_path, cache)

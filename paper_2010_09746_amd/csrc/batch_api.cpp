@@ -1,11 +1,14 @@
-// Batching form (C boundary): many independent circuits of different sizes
-// compiled together and executed level by level (one persistent launch per
-// pass level), the whole sequence captured once in a HIP graph and replayed.
+// Batching form (C boundary): many independent circuits of different sizes,
+// each compiled with its own tile size, executed by one persistent launch
+// that takes ranges of tiles from a ticketed work list and waits, per item,
+// for the circuit's previous pass.  The launch (after a small kernel that
+// clears its counters) is captured once in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <vector>
@@ -15,40 +18,146 @@
 
 using namespace qsim;
 
-struct qs_batch {
-    int count = 0;
-    qs_dtype dt = QS_C64;
-    qs_batch_opts opts{};
-    int log_r = 0, log_nt = 0, grid = 0;
-    hipStream_t stream = nullptr;
-    std::vector<int> n;
-    std::vector<uint64_t> start;  // element offset of each state
-    uint64_t total = 0;
-    std::vector<BatchPass> passes;
-    std::vector<BatchItem> items;
-    std::vector<uint32_t> level_start;  // items of level L: [level_start[L], level_start[L+1])
-    std::vector<std::vector<int>> circ_passes;  // pass indices of each circuit, in order
-    std::vector<std::vector<int>> level_solo;   // passes of level L run as launches of their own
-    uint64_t solo_tiles = 1ull << 12;           // 0: every pass in the level launch
-    size_t items_cap = 0;                       // BatchItem capacity of d_items
-    std::vector<TileOp> ops;
-    std::vector<uint64_t> part_off;
-    std::vector<uint32_t> part_cnt;
-    uint64_t n_partials = 0;
-    // device
-    void *d_state = nullptr;
-    TileOp *d_ops = nullptr;
-    BatchPass *d_passes = nullptr;
-    BatchItem *d_items = nullptr;
-    double *d_partials = nullptr, *d_out = nullptr;
-    uint64_t *d_starts = nullptr, *d_part_off = nullptr;
-    uint32_t *d_part_cnt = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    qs_batch_stats stats{};
+namespace {
+
+// Host-only plan of a batch: compiled programs, the pass table (circuit by
+// circuit) and the work items in ticket order.
+struct PlanPass {
+    int circuit = 0, level = 0, k = 0, last = 0;
+    uint32_t tiles = 0;
+    const Launch *launch = nullptr;  // NULL: the empty pass of a circuit without gates
 };
 
-namespace {
+struct BatchPlan {
+    std::vector<Program> progs;
+    std::vector<int> k;                          // tile qubits of each circuit
+    std::vector<PlanPass> passes;
+    std::vector<std::vector<int>> circ_passes;   // pass indices of each circuit, in order
+    std::vector<QueueItem> items;
+};
+
+constexpr int BATCH_MIN_TILE = QUEUE_LOG_NT + QUEUE_MIN_SHAPE;  // 9
+constexpr int BATCH_MAX_TILE = QUEUE_LOG_NT + QUEUE_MAX_SHAPE;  // 12
+
+void check_opts(const qs_batch_opts &o)
+{
+    if (o.k_tile < BATCH_MIN_TILE || o.k_tile > BATCH_MAX_TILE)
+        fail(QS_ERR_ARG, "k_tile of a batch must be in [9, 12]");
+    if (o.max_swaps < 0 || o.pinned < 0 || o.max_fuse < 0 || o.chunk < 0 || o.wg_per_cu < 0 || o.wait_ms < -1)
+        fail(QS_ERR_ARG, "negative batch option");
+}
+
+// Compile every circuit (host threads) with k = min(n, k_tile) and order the
+// work: level by level (the L-th pass of every circuit), and within a level
+// the circuits with the most work left first.  Every item of a circuit's
+// pass L comes after every item of its pass L - 1, which the executor's
+// progress argument needs.
+void plan_batch(int count, const int *n, const qs_gate *const *gates, const int64_t *n_gates, qs_dtype dt,
+                const qs_batch_opts &o, BatchPlan &bp)
+{
+    check_opts(o);
+    bp.progs.assign(count, Program());
+    bp.k.resize(count);
+    for (int c = 0; c < count; ++c) {
+        if (n[c] < BATCH_MIN_TILE || n[c] > MAX_QUBITS)
+            fail(QS_ERR_ARG, "every circuit of a batch needs 9 <= n <= 34 (circuit " + std::to_string(c) + ")");
+        if (n_gates[c] < 0 || (n_gates[c] > 0 && !gates[c]))
+            fail(QS_ERR_ARG, "bad gate array (circuit " + std::to_string(c) + ")");
+        bp.k[c] = std::min(n[c], o.k_tile);
+    }
+    std::vector<std::string> errs(count);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nth; ++w)
+        th.emplace_back([&, w] {
+            for (int c = (int)w; c < count; c += (int)nth) {
+                qs_run_opts ro{};
+                ro.form = QS_FORM_PASS;
+                ro.k_tile = bp.k[c];
+                ro.max_swaps = std::max(1, o.max_swaps);
+                ro.pinned = std::min(o.pinned, bp.k[c]);
+                ro.perm_exec = QS_PERM_RELABEL;
+                ro.max_fuse = o.max_fuse;
+                ro.reg_bits = bp.k[c] - QUEUE_LOG_NT;
+                try {
+                    compile_program(gates[c], n_gates[c], n[c], dt, nullptr, ro, bp.progs[c]);
+                } catch (const Error &e) {
+                    errs[c] = e.msg;
+                }
+            }
+        });
+    for (auto &t : th)
+        t.join();
+    for (int c = 0; c < count; ++c)
+        if (!errs[c].empty())
+            fail(QS_ERR_ARG, "circuit " + std::to_string(c) + ": " + errs[c]);
+
+    // pass table: each circuit's tile passes; a circuit without gates gets
+    // one empty pass, so that its state and read-out are still produced
+    bp.passes.clear();
+    bp.circ_passes.assign(count, {});
+    for (int c = 0; c < count; ++c) {
+        const Program &p = bp.progs[c];
+        std::vector<const Launch *> tl;
+        for (const Launch &L : p.launches) {
+            if (L.type != L_TILE || L.k != bp.k[c] || L.log_nt != QUEUE_LOG_NT)
+                fail(QS_ERR_UNSUPPORTED, "batch circuit " + std::to_string(c) + " needs a launch other than a tile pass");
+            tl.push_back(&L);
+        }
+        const int np = std::max<int>(1, (int)tl.size());
+        for (int i = 0; i < np; ++i) {
+            PlanPass P;
+            P.circuit = c;
+            P.level = i;
+            P.k = bp.k[c];
+            P.last = i == np - 1;
+            P.tiles = (uint32_t)(1ull << (n[c] - bp.k[c]));
+            P.launch = tl.empty() ? nullptr : tl[i];
+            bp.circ_passes[c].push_back((int)bp.passes.size());
+            bp.passes.push_back(P);
+        }
+    }
+    // work items: level by level; within a level, circuits by the amplitudes
+    // their remaining passes touch (most first)
+    const uint32_t chunk = (uint32_t)std::max(1, o.chunk);
+    size_t max_np = 0;
+    for (auto &v : bp.circ_passes)
+        max_np = std::max(max_np, v.size());
+    std::vector<std::vector<double>> left(count);
+    for (int c = 0; c < count; ++c) {
+        const auto &v = bp.circ_passes[c];
+        left[c].assign(v.size() + 1, 0.0);
+        for (int i = (int)v.size() - 1; i >= 0; --i)
+            left[c][i] = left[c][i + 1] + std::ldexp(1.0, n[c]);
+    }
+    bp.items.clear();
+    std::vector<int> order(count);
+    for (size_t lvl = 0; lvl < max_np; ++lvl) {
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const double la = lvl < bp.circ_passes[a].size() ? left[a][lvl] : -1.0;
+            const double lb = lvl < bp.circ_passes[b].size() ? left[b][lvl] : -1.0;
+            return la > lb;
+        });
+        for (int c : order) {
+            if (lvl >= bp.circ_passes[c].size())
+                continue;
+            const int pi = bp.circ_passes[c][lvl];
+            const PlanPass &P = bp.passes[pi];
+            const int dep = lvl > 0 ? bp.circ_passes[c][lvl - 1] : -1;
+            for (uint32_t t = 0; t < P.tiles; t += chunk) {
+                QueueItem it{};
+                it.pass = (uint32_t)pi;
+                it.t0 = t;
+                it.t1 = std::min(P.tiles, t + chunk);
+                it.dep = dep;
+                it.need = dep >= 0 ? bp.passes[dep].tiles : 0;
+                it.shape = (uint32_t)(P.k - QUEUE_LOG_NT);
+                bp.items.push_back(it);
+            }
+        }
+    }
+}
 
 void hipchk(hipError_t e, const char *what)
 {
@@ -56,28 +165,6 @@ void hipchk(hipError_t e, const char *what)
         (void)hipGetLastError();
         fail(e == hipErrorOutOfMemory ? QS_ERR_OOM : QS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
     }
-}
-
-template <typename T> void upload(T *&dst, const std::vector<T> &src, const char *what)
-{
-    hipchk(hipMalloc(&dst, std::max<size_t>(1, src.size()) * sizeof(T)), what);
-    if (!src.empty())
-        hipchk(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), what);
-}
-
-void free_batch(qs_batch *b)
-{
-    if (b->exec)
-        (void)hipGraphExecDestroy(b->exec);
-    if (b->graph)
-        (void)hipGraphDestroy(b->graph);
-    void *ptrs[] = {b->d_state, b->d_ops, b->d_passes, b->d_items, b->d_partials,
-                    b->d_out, b->d_starts, b->d_part_off, b->d_part_cnt};
-    for (void *p : ptrs)
-        if (p)
-            (void)hipFree(p);
-    if (b->stream)
-        (void)hipStreamDestroy(b->stream);
 }
 
 template <typename F> qs_status guard(F &&f)
@@ -101,70 +188,153 @@ template <typename F> qs_status guard(F &&f)
     }
 }
 
-// Work items of each pass level.  A pass of at least solo_tiles tiles that is
-// not its circuit's last (the last one also produces the read-out partials)
-// goes to level_solo instead: it fills the device by itself and runs as a
-// tile-pass launch (one workgroup per tile) after the level launch.
-void build_levels(qs_batch *b)
+}  // namespace
+
+struct qs_batch {
+    int count = 0;
+    qs_dtype dt = QS_C64;
+    qs_batch_opts opts{};
+    int grid = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    std::vector<int> n;
+    std::vector<uint64_t> start;  // element offset of each state
+    uint64_t total = 0;
+    std::vector<BatchPass> passes;
+    std::vector<QueueItem> items;
+    std::vector<uint64_t> part_off;
+    std::vector<uint32_t> part_cnt;
+    uint64_t n_partials = 0;
+    uint64_t n_words = 0;         // ticket + per-pass counters
+    // device
+    void *d_state = nullptr;
+    TileOp *d_ops = nullptr;
+    BatchPass *d_passes = nullptr;
+    QueueItem *d_items = nullptr;
+    uint32_t *d_words = nullptr;
+    double *d_partials = nullptr, *d_out = nullptr;
+    uint64_t *d_part_off = nullptr;
+    uint32_t *d_part_cnt = nullptr;
+    uint32_t *h_flags = nullptr;  // host-pinned: [0] abort, [1] a wait gave up
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    qs_batch_stats stats{};
+};
+
+namespace {
+
+template <typename T> void upload(T *&dst, const std::vector<T> &src, const char *what)
 {
-    const uint32_t chunk = (uint32_t)std::max(1, b->opts.chunk);
-    size_t max_np = 0;
-    for (auto &v : b->circ_passes)
-        max_np = std::max(max_np, v.size());
-    b->items.clear();
-    b->level_start.clear();
-    b->level_solo.assign(max_np, {});
-    for (size_t lvl = 0; lvl < max_np; ++lvl) {
-        b->level_start.push_back((uint32_t)b->items.size());
-        for (int c = 0; c < b->count; ++c) {
-            if (lvl >= b->circ_passes[c].size())
-                continue;
-            const int pi = b->circ_passes[c][lvl];
-            const BatchPass &P = b->passes[pi];
-            const uint32_t nt = P.ntiles;
-            if (b->solo_tiles && nt >= b->solo_tiles && !P.last) {
-                b->level_solo[lvl].push_back(pi);
-                continue;
-            }
-            for (uint32_t t = 0; t < nt; t += chunk)
-                b->items.push_back(BatchItem{(uint32_t)pi, t, std::min(nt, t + chunk), 0});
-        }
-    }
-    b->level_start.push_back((uint32_t)b->items.size());
-    b->stats.n_items = (int64_t)b->items.size();
+    hipchk(hipMalloc(&dst, std::max<size_t>(1, src.size()) * sizeof(T)), what);
+    if (!src.empty())
+        hipchk(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), what);
+}
+
+void free_batch(qs_batch *b)
+{
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    void *ptrs[] = {b->d_state, b->d_ops, b->d_passes, b->d_items, b->d_words,
+                    b->d_partials, b->d_out, b->d_part_off, b->d_part_cnt};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    if (b->h_flags)
+        (void)hipHostFree(b->h_flags);
+    if (b->done_ev)
+        (void)hipEventDestroy(b->done_ev);
+    if (b->stream)
+        (void)hipStreamDestroy(b->stream);
+}
+
+QueueArgs queue_args(qs_batch *b)
+{
+    QueueArgs q{};
+    q.passes = b->d_passes;
+    q.items = b->d_items;
+    q.n_items = (uint32_t)b->items.size();
+    q.n_circuits = (uint32_t)b->count;
+    q.next = b->d_words;
+    q.done = b->d_words + 4;
+    q.flags = b->h_flags;
+    q.partials = b->d_partials;
+    q.out = b->d_out;
+    q.part_off = b->d_part_off;
+    q.part_cnt = b->d_part_cnt;
+    const int ms = b->opts.wait_ms > 0 ? b->opts.wait_ms : b->opts.wait_ms < 0 ? 0 : 2000;
+    q.wait_ticks = (uint64_t)ms * 100000ull;  // 100 MHz; 0: every wait gives up at once
+    return q;
 }
 
 void enqueue(qs_batch *b)
 {
-    launch_batch_init(b->d_state, b->dt, b->total, b->d_starts, b->count, b->stream);
-    for (size_t L = 0; L + 1 < b->level_start.size(); ++L) {
-        BatchArgs a{};
-        a.passes = b->d_passes;
-        a.items = b->d_items;
-        a.i0 = b->level_start[L];
-        a.i1 = b->level_start[L + 1];
-        a.partials = b->d_partials;
-        const int grid = (int)std::min<uint32_t>((uint32_t)b->grid, a.i1 - a.i0);
-        if (grid > 0) {
-            if (b->dt == QS_C64)
-                launch_batch_f32(a, b->log_r, b->log_nt, grid, b->stream);
-            else
-                launch_batch_f64(a, b->log_r, b->log_nt, grid, b->stream);
+    launch_queue_reset(b->d_words, b->n_words, b->stream);
+    const QueueArgs q = queue_args(b);
+    const int grid = (int)std::min<size_t>((size_t)b->grid, std::max<size_t>(1, b->items.size()));
+    if (b->dt == QS_C64)
+        launch_batch_queue_f32(q, grid, b->stream);
+    else
+        launch_batch_queue_f64(q, grid, b->stream);
+}
+
+// Wait for the last run, giving up after a bound: then the host sets the
+// abort flag, which every dependency wait of the launch checks, and waits for
+// the launch to drain.
+void wait_run(qs_batch *b)
+{
+    hipchk(hipEventRecord(b->done_ev, b->stream), "hipEventRecord");
+    const auto t0 = std::chrono::steady_clock::now();
+    const double limit_s = 60.0 + 4.0 * (b->opts.wait_ms > 0 ? b->opts.wait_ms : 2000) / 1000.0;
+    for (;;) {
+        const hipError_t e = hipEventQuery(b->done_ev);
+        if (e == hipSuccess)
+            break;
+        if (e != hipErrorNotReady)
+            hipchk(e, "hipEventQuery");
+        if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit_s) {
+            __atomic_store_n(&b->h_flags[0], 1u, __ATOMIC_SEQ_CST);
+            hipchk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+            __atomic_store_n(&b->h_flags[0], 0u, __ATOMIC_SEQ_CST);
+            fail(QS_ERR_HIP, "batch run did not finish in time; its waits were aborted");
         }
-        for (int pi : b->level_solo[L]) {
-            const BatchPass &P = b->passes[pi];
-            if (b->dt == QS_C64)
-                launch_tile_f32(P.t, P.ntiles, b->log_r, b->log_nt, b->stream);
-            else
-                launch_tile_f64(P.t, P.ntiles, b->log_r, b->log_nt, b->stream);
-        }
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
-    launch_batch_reduce(b->d_partials, b->d_part_off, b->d_part_cnt, b->count, b->d_out, b->stream);
+    if (__atomic_load_n(&b->h_flags[1], __ATOMIC_SEQ_CST) != 0u) {
+        __atomic_store_n(&b->h_flags[1], 0u, __ATOMIC_SEQ_CST);
+        fail(QS_ERR_HIP, "a work item of the batch launch waited too long for its circuit's previous pass");
+    }
 }
 
 }  // namespace
 
 extern "C" {
+
+qs_status qs_batch_plan(int count, const int *n_qubits, const qs_gate *const *gates, const int64_t *n_gates,
+                        qs_dtype dt, const qs_batch_opts *opts, qs_batch_pass_info *passes, int64_t pass_cap,
+                        int64_t *n_passes, qs_batch_item_info *items, int64_t item_cap, int64_t *n_items)
+{
+    return guard([&] {
+        if (count < 1 || !n_qubits || !gates || !n_gates || !opts || !n_passes || !n_items)
+            fail(QS_ERR_ARG, "bad arguments");
+        if (dt != QS_C64 && dt != QS_C128)
+            fail(QS_ERR_ARG, "unknown dtype");
+        BatchPlan bp;
+        plan_batch(count, n_qubits, gates, n_gates, dt, *opts, bp);
+        *n_passes = (int64_t)bp.passes.size();
+        *n_items = (int64_t)bp.items.size();
+        for (int64_t i = 0; passes && i < pass_cap && i < *n_passes; ++i) {
+            const PlanPass &P = bp.passes[i];
+            passes[i] = qs_batch_pass_info{P.circuit, P.level, P.k, P.last, (int64_t)P.tiles};
+        }
+        for (int64_t i = 0; items && i < item_cap && i < *n_items; ++i) {
+            const QueueItem &it = bp.items[i];
+            items[i] = qs_batch_item_info{(int32_t)it.pass, it.dep, (int64_t)it.t0, (int64_t)it.t1,
+                                          (int64_t)it.need};
+        }
+    });
+}
 
 qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *gates, const int64_t *n_gates,
                           qs_dtype dt, const qs_batch_opts *opts, qs_batch **out)
@@ -176,125 +346,82 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
         if (dt != QS_C64 && dt != QS_C128)
             fail(QS_ERR_ARG, "unknown dtype");
         const qs_batch_opts o = *opts;
-        const int K = o.k_tile;
         const size_t eb = dt == QS_C64 ? 8 : 16;
-        if (K < MIN_TILE_BITS || (eb << K) > MAX_BATCH_TILE_BYTES)
-            fail(QS_ERR_ARG, "k_tile out of range for the batching form");
-        for (int c = 0; c < count; ++c)
-            if (n_qubits[c] < K || n_qubits[c] > MAX_QUBITS)
-                fail(QS_ERR_ARG, "every circuit needs k_tile <= n <= 34 (circuit " + std::to_string(c) + ")");
         auto t0 = std::chrono::steady_clock::now();
+        BatchPlan bp;
+        plan_batch(count, n_qubits, gates, n_gates, dt, o, bp);
         auto *b = new qs_batch();
         try {
             b->count = count;
             b->dt = dt;
             b->opts = o;
-            tile_shape(K, dt, o.reg_bits, &b->log_r, &b->log_nt);
             b->n.assign(n_qubits, n_qubits + count);
             b->start.resize(count);
             for (int c = 0; c < count; ++c) {
                 b->start[c] = b->total;
                 b->total += 1ull << b->n[c];
             }
-            // compile every circuit (host threads)
-            std::vector<Program> progs(count);
-            qs_run_opts ro{};
-            ro.form = QS_FORM_PASS;
-            ro.k_tile = K;
-            ro.max_swaps = std::max(1, o.max_swaps);
-            ro.pinned = std::min(o.pinned, K);
-            ro.perm_exec = QS_PERM_RELABEL;
-            ro.max_fuse = o.max_fuse;
-            ro.reg_bits = b->log_r;
-            std::vector<std::string> errs(count);
-            const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-            std::vector<std::thread> th;
-            for (unsigned w = 0; w < nth; ++w)
-                th.emplace_back([&, w] {
-                    for (int c = (int)w; c < count; c += (int)nth) {
-                        try {
-                            compile_program(gates[c], n_gates[c], b->n[c], dt, nullptr, ro, progs[c]);
-                        } catch (const Error &e) {
-                            errs[c] = e.msg;
-                        }
-                    }
-                });
-            for (auto &t : th)
-                t.join();
-            for (int c = 0; c < count; ++c)
-                if (!errs[c].empty())
-                    fail(QS_ERR_ARG, "circuit " + std::to_string(c) + ": " + errs[c]);
-
-            // device buffers whose addresses the pass table needs
             hipchk(hipMalloc(&b->d_state, b->total * eb), "hipMalloc(batch states)");
-            size_t n_ops = 0;
-            for (auto &p : progs)
-                n_ops += p.ops.size();
-            hipchk(hipMalloc(&b->d_ops, std::max<size_t>(1, n_ops) * sizeof(TileOp)), "hipMalloc(batch ops)");
-
-            // pass table: each circuit's tile passes; a circuit without gates
-            // gets one empty pass so that its read-out is still produced
-            std::vector<std::vector<int>> circ_passes(count);
-            size_t op_base = 0;
+            std::vector<size_t> op_base(count, 0);
+            std::vector<TileOp> ops;
             for (int c = 0; c < count; ++c) {
-                Program &p = progs[c];
-                const uint64_t ntiles = 1ull << (b->n[c] - K);
-                std::vector<const Launch *> tl;
-                for (const Launch &L : p.launches) {
-                    if (L.type != L_TILE)
-                        fail(QS_ERR_UNSUPPORTED, "batch circuit " + std::to_string(c) + " needs a non-tile launch");
-                    tl.push_back(&L);
-                }
-                const int np = std::max<int>(1, (int)tl.size());
-                b->part_off.push_back(b->n_partials);
-                b->part_cnt.push_back((uint32_t)ntiles);
-                for (int i = 0; i < np; ++i) {
-                    BatchPass P{};
-                    P.t.state = static_cast<char *>(b->d_state) + b->start[c] * eb;
-                    if (!tl.empty()) {
-                        tile_args_from_launch(*tl[i], P.t);
-                        P.t.ops = b->d_ops + op_base + tl[i]->op_begin;
-                    } else {
-                        tile_args_identity(K, b->log_nt, b->log_r, P.t);
-                        P.t.ops = b->d_ops;
-                    }
-                    P.t.n_hi = b->n[c] - K;
-                    P.ntiles = (uint32_t)ntiles;
-                    P.last = i == np - 1;
-                    P.zpos = p.sigma_final[0];
-                    P.part = b->n_partials;
-                    circ_passes[c].push_back((int)b->passes.size());
-                    b->passes.push_back(P);
-                }
-                b->n_partials += ntiles;
-                b->ops.insert(b->ops.end(), p.ops.begin(), p.ops.end());
-                op_base += p.ops.size();
-                b->stats.n_passes += np;
-                b->stats.n_tiles += (int64_t)np * (int64_t)ntiles;
-                b->stats.n_gates += p.stats.n_gates;
-                b->stats.n_perm += p.stats.n_perm;
+                op_base[c] = ops.size();
+                ops.insert(ops.end(), bp.progs[c].ops.begin(), bp.progs[c].ops.end());
             }
-            // work items ordered by pass level
-            b->circ_passes = std::move(circ_passes);
-            build_levels(b);
-            b->items_cap = std::max<size_t>(1, b->items.size());
-
-            if (!b->ops.empty())
-                hipchk(hipMemcpy(b->d_ops, b->ops.data(), b->ops.size() * sizeof(TileOp), hipMemcpyHostToDevice),
-                       "hipMemcpy(batch ops)");
+            upload(b->d_ops, ops, "batch ops");
+            // read-out partials: two per tile of each circuit's last pass
+            for (int c = 0; c < count; ++c) {
+                b->part_off.push_back(b->n_partials);
+                b->part_cnt.push_back((uint32_t)(1ull << (b->n[c] - bp.k[c])));
+                b->n_partials += b->part_cnt.back();
+            }
+            for (const PlanPass &P : bp.passes) {
+                const int c = P.circuit;
+                BatchPass D{};
+                if (P.launch) {
+                    tile_args_from_launch(*P.launch, D.t);
+                    D.t.ops = b->d_ops + op_base[c] + P.launch->op_begin;
+                } else {
+                    tile_args_identity(P.k, QUEUE_LOG_NT, P.k - QUEUE_LOG_NT, D.t);
+                    D.t.ops = b->d_ops;
+                }
+                D.t.state = static_cast<char *>(b->d_state) + b->start[c] * eb;
+                D.t.n_hi = b->n[c] - P.k;
+                if (P.level == 0)
+                    D.t.io |= 16u;  // the first pass starts from |0...0> instead of reading the state
+                D.ntiles = P.tiles;
+                D.last = P.last;
+                D.zpos = bp.progs[c].sigma_final[0];
+                D.circuit = c;
+                D.part = b->part_off[c];
+                b->passes.push_back(D);
+                b->stats.n_tiles += P.tiles;
+            }
+            b->items = bp.items;
+            for (int c = 0; c < count; ++c) {
+                b->stats.n_gates += bp.progs[c].stats.n_gates;
+                b->stats.n_perm += bp.progs[c].stats.n_perm;
+            }
+            b->stats.n_passes = (int64_t)bp.passes.size();
+            b->stats.n_items = (int64_t)b->items.size();
             upload(b->d_passes, b->passes, "batch passes");
             upload(b->d_items, b->items, "batch items");
-            upload(b->d_starts, b->start, "batch starts");
             upload(b->d_part_off, b->part_off, "batch partial offsets");
             upload(b->d_part_cnt, b->part_cnt, "batch partial counts");
+            b->n_words = 4 + b->passes.size();
+            hipchk(hipMalloc(&b->d_words, b->n_words * sizeof(uint32_t)), "hipMalloc(batch counters)");
             hipchk(hipMalloc(&b->d_partials, std::max<uint64_t>(1, b->n_partials) * 2 * sizeof(double)),
                    "hipMalloc(partials)");
             hipchk(hipMalloc(&b->d_out, (size_t)count * 2 * sizeof(double)), "hipMalloc(batch out)");
+            hipchk(hipHostMalloc(reinterpret_cast<void **>(&b->h_flags), 4 * sizeof(uint32_t), hipHostMallocCoherent),
+                   "hipHostMalloc(batch flags)");
+            std::memset(b->h_flags, 0, 4 * sizeof(uint32_t));
             hipchk(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate");
+            hipchk(hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming), "hipEventCreate");
             int dev = 0, cus = 0;
             hipchk(hipGetDevice(&dev), "hipGetDevice");
             hipchk(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
-            b->grid = std::max(1, cus * std::max(1, o.wg_per_cu));
+            b->grid = std::max(1, cus * (o.wg_per_cu > 0 ? o.wg_per_cu : 4));
             b->stats.state_bytes = (double)(b->total * eb);
         } catch (...) {
             free_batch(b);
@@ -304,34 +431,6 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
         auto t1 = std::chrono::steady_clock::now();
         b->stats.compile_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         *out = b;
-    });
-}
-
-qs_status qs_batch_set_solo_tiles(qs_batch *b, int64_t min_tiles)
-{
-    return guard([&] {
-        if (!b || min_tiles < 0)
-            fail(QS_ERR_ARG, "bad arguments");
-        hipchk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-        b->solo_tiles = (uint64_t)min_tiles;
-        build_levels(b);
-        if (b->items.size() > b->items_cap) {
-            hipchk(hipFree(b->d_items), "hipFree(batch items)");
-            b->d_items = nullptr;
-            hipchk(hipMalloc(&b->d_items, b->items.size() * sizeof(BatchItem)), "hipMalloc(batch items)");
-            b->items_cap = b->items.size();
-        }
-        if (!b->items.empty())
-            hipchk(hipMemcpy(b->d_items, b->items.data(), b->items.size() * sizeof(BatchItem),
-                             hipMemcpyHostToDevice),
-                   "hipMemcpy(batch items)");
-        // the captured launch sequence no longer matches: capture again at the next run
-        if (b->exec)
-            hipchk(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
-        b->exec = nullptr;
-        if (b->graph)
-            hipchk(hipGraphDestroy(b->graph), "hipGraphDestroy");
-        b->graph = nullptr;
     });
 }
 
@@ -367,6 +466,7 @@ qs_status qs_batch_results(qs_batch *b, double *z0, double *norms)
     return guard([&] {
         if (!b)
             fail(QS_ERR_ARG, "batch is NULL");
+        wait_run(b);
         std::vector<double> out((size_t)b->count * 2);
         hipchk(hipMemcpyAsync(out.data(), b->d_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream),
                "hipMemcpyAsync");
@@ -388,6 +488,9 @@ qs_status qs_batch_read_state(qs_batch *b, int circuit, double *out)
         const int n = b->n[circuit];
         if (n > 26)
             fail(QS_ERR_ARG, "qs_batch_read_state is limited to n <= 26");
+        wait_run(b);
+        // placements are relabelled, so every state stays in its starting
+        // (identity) placement: physical order is logical order
         const uint64_t N = 1ull << n;
         const size_t eb = b->dt == QS_C64 ? 8 : 16;
         std::vector<unsigned char> raw(N * eb);
@@ -423,7 +526,7 @@ qs_status qs_batch_synchronize(qs_batch *b)
     return guard([&] {
         if (!b)
             fail(QS_ERR_ARG, "batch is NULL");
-        hipchk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        wait_run(b);
     });
 }
 
@@ -432,7 +535,8 @@ qs_status qs_batch_destroy(qs_batch *b)
     return guard([&] {
         if (!b)
             return;
-        (void)hipStreamSynchronize(b->stream);
+        if (b->stream)
+            (void)hipStreamSynchronize(b->stream);  // a run in flight drains (its waits are bounded)
         free_batch(b);
         delete b;
     });

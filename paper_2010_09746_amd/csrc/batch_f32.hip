@@ -6,6 +6,12 @@ namespace qsim {
 
 namespace {
 
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t *p, uint64_t words)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (uint64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_zero_u64(uint64_t *p, uint64_t words)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (uint64_t)gridDim.x * 256)
@@ -82,5 +88,15 @@ void launch_batch_reduce(const double *partials, const uint64_t *part_off, const
     hipLaunchKernelGGL(k_batch_reduce, dim3(count), dim3(256), 0, st, partials, part_off, part_cnt, out);
     check_launch("batch reduce");
 }
+
+void launch_queue_reset(uint32_t *words, uint64_t n_words, hipStream_t st)
+{
+    // a fill kernel, not a memset: the launch is recorded into a HIP graph
+    const uint64_t blocks = std::min<uint64_t>(1024, (n_words + 255) / 256);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::max<uint64_t>(1, blocks)), dim3(256), 0, st, words, n_words);
+    check_launch("batch queue reset");
+}
+
+void launch_batch_queue_f32(const QueueArgs &q, int grid, hipStream_t st) { launch_batch_queue_t<float>(q, grid, st); }
 
 }  // namespace qsim

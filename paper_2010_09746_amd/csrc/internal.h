@@ -49,8 +49,32 @@ struct BatchPass {
     uint32_t ntiles;  // tiles of this pass = 2^(n - k)
     int32_t last;     // 1: write read-out partials after the pass
     int32_t zpos;     // physical position of qubit 0
-    int32_t pad;
+    int32_t circuit;  // index of the pass's circuit
     uint64_t part;    // first read-out partial (two doubles per tile) of the circuit
+};
+
+// Single-launch batch executor.  Work item: tiles [t0, t1) of pass `pass`,
+// whose tile has 2^(8 + shape) amplitudes (256 threads x 2^shape).  It may
+// start once pass `dep` (the circuit's previous pass; -1: none) has completed
+// `need` tiles (all of them).  Items are listed in an order in which every
+// dependency precedes its dependents.
+struct QueueItem {
+    uint32_t pass, t0, t1;
+    int32_t dep;
+    uint32_t need, shape, pad0, pad1;
+};
+struct QueueArgs {
+    const BatchPass *passes;
+    const QueueItem *items;
+    uint32_t n_items, n_circuits;
+    uint32_t *next;            // device: the next ticket (zero before a run)
+    uint32_t *done;            // device: tiles completed per pass (zero before a run)
+    uint32_t *flags;           // host-pinned: [0] abort (set by the host), [1] set by a wait that gave up
+    double *partials;          // two per tile of each circuit's last pass
+    double *out;               // two per circuit: <Z_0>, norm
+    const uint64_t *part_off;  // per circuit: its first partial
+    const uint32_t *part_cnt;  // per circuit: its number of partials (tiles of the last pass)
+    uint64_t wait_ticks;       // longest wait for a dependency, in 100 MHz clock ticks
 };
 
 // A range of tiles of one pass: the unit of work of a level launch.

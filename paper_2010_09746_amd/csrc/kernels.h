@@ -34,6 +34,15 @@ void launch_batch_f64(const BatchArgs &b, int log_r, int log_nt, int grid, hipSt
 void launch_batch_reduce(const double *partials, const uint64_t *part_off, const uint32_t *part_cnt, int count,
                          double *out, hipStream_t st);
 
+// Single-launch batch executor: zero the ticket and the per-pass completion
+// counters, then one persistent launch of `grid` workgroups over every work
+// item (see QueueArgs).
+void launch_queue_reset(uint32_t *words, uint64_t n_words, hipStream_t st);
+void launch_batch_queue_f32(const QueueArgs &q, int grid, hipStream_t st);
+void launch_batch_queue_f64(const QueueArgs &q, int grid, hipStream_t st);
+// largest register bits of a queue item's tile (2^(8 + shape) amplitudes)
+constexpr int QUEUE_MIN_SHAPE = 1, QUEUE_MAX_SHAPE = 4, QUEUE_LOG_NT = 8;
+
 // Read-out: norm and position sums S_p = sum_j |v_j|^2 bit_p(j), written to
 // out_dev[0] (norm) and out_dev[1 + p].  work_dev holds the block partials.
 size_t zsum_work_doubles(int n);

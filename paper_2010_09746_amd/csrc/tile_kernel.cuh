@@ -460,8 +460,10 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     };
 
     // Tiles t_first, t_first + t_step, ... below t_end.  A is TileArgs, read
-    // from kernel arguments or from device memory.
-    template <bool PF, typename A>
+    // from kernel arguments or from device memory.  With BASIS, a pass whose
+    // TileArgs::io has bit 4 set reads nothing: its tiles start as the basis
+    // state |0...0> (1 at physical index 0, 0 elsewhere).
+    template <bool PF, bool BASIS = false, typename A>
     static __device__ __forceinline__ void run_range(const A &a, unsigned char *lds, uint64_t t_first, uint64_t t_end,
                                                      uint64_t t_step, Readout ro)
     {
@@ -484,6 +486,16 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
         C v[NR];
         auto load = [&](C(&dst)[NR], uint64_t tile) {
             const C *src = st + tile_base(a, tile) + lane_ld;
+            if constexpr (BASIS) {
+                if (a.io & 16u) {
+                    const bool origin = (src == st);
+                    for_slots<uint64_t>(pbit_ld, [&](int j, uint64_t o) {
+                        dst[j].x = (origin && o == 0) ? R(1) : R(0);
+                        dst[j].y = R(0);
+                    });
+                    return;
+                }
+            }
             // with STREAM (one pass over an HBM-resident state, every amplitude
             // read once and written once, whole 128-byte lines per access)
             // loads and stores are non-temporal: +3-6% bandwidth on passes

@@ -44,7 +44,7 @@ EXPORTS = [
     "qs_program_instructions", "qs_run_program", "qs_run_circuit", "qs_read_amplitudes", "qs_read_state",
     "qs_expect_z", "qs_norm", "qs_fidelity", "qs_synchronize", "qs_profile_enable", "qs_profile_read",
     "qs_batch_create", "qs_batch_run", "qs_batch_results", "qs_batch_read_state", "qs_batch_get_stats",
-    "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_set_solo_tiles",
+    "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_plan",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
     "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
     "qs_run_program_noalloc",
@@ -73,7 +73,18 @@ class qs_program_stats(ctypes.Structure):
 class qs_batch_opts(ctypes.Structure):
     _fields_ = [("k_tile", ctypes.c_int32), ("max_swaps", ctypes.c_int32), ("pinned", ctypes.c_int32),
                 ("reg_bits", ctypes.c_int32), ("max_fuse", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("wait_ms", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class qs_batch_pass_info(ctypes.Structure):
+    _fields_ = [("circuit", ctypes.c_int32), ("level", ctypes.c_int32), ("k_tile", ctypes.c_int32),
+                ("last", ctypes.c_int32), ("tiles", ctypes.c_int64)]
+
+
+class qs_batch_item_info(ctypes.Structure):
+    _fields_ = [("pass_", ctypes.c_int32), ("dep", ctypes.c_int32), ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
+                ("need", ctypes.c_int64)]
 
 
 class qs_batch_stats(ctypes.Structure):
@@ -135,11 +146,14 @@ def load() -> ctypes.CDLL:
     L.qs_batch_get_stats.argtypes = [_vp, ctypes.POINTER(qs_batch_stats)]
     L.qs_batch_synchronize.argtypes = [_vp]
     L.qs_batch_destroy.argtypes = [_vp]
+    L.qs_batch_plan.argtypes = [ctypes.c_int, _ip, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.c_int, ctypes.POINTER(qs_batch_opts), ctypes.POINTER(qs_batch_pass_info),
+                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(qs_batch_item_info),
+                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.qs_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(qs_batch_opts), ctypes.c_size_t, ctypes.c_int,
                                    ctypes.c_int, ctypes.POINTER(_vp)]
     L.qs_server_destroy.argtypes = [_vp]
     L.qs_server_set_solo_tiles.argtypes = [_vp, ctypes.c_int64]
-    L.qs_batch_set_solo_tiles.argtypes = [_vp, ctypes.c_int64]
     L.qs_server_fits.argtypes = [_vp, ctypes.c_int, _ip]
     L.qs_server_admit.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -367,11 +381,12 @@ def qs_profile_read() -> dict:
     return out
 
 
-def make_batch_opts(k_tile=10, max_swaps=8, pinned=3, reg_bits=0, max_fuse=0, wg_per_cu=8, chunk=8,
-                    use_graph=1) -> qs_batch_opts:
+def make_batch_opts(k_tile=12, max_swaps=8, pinned=3, reg_bits=0, max_fuse=0, wg_per_cu=4, chunk=4,
+                    use_graph=1, wait_ms=0) -> qs_batch_opts:
     o = qs_batch_opts()
     o.k_tile, o.max_swaps, o.pinned, o.reg_bits = k_tile, max_swaps, pinned, reg_bits
     o.max_fuse, o.wg_per_cu, o.chunk, o.use_graph = max_fuse, wg_per_cu, chunk, use_graph
+    o.wait_ms = wait_ms
     return o
 
 
@@ -386,6 +401,27 @@ def qs_batch_create(circuits, dtype, opts: qs_batch_opts) -> int:
     _chk(load().qs_batch_create(cnt, ns.ctypes.data_as(_ip), ptrs, ngs, _dtype_code(dtype), ctypes.byref(opts),
                                 ctypes.byref(h)))
     return h.value
+
+
+def qs_batch_plan(circuits, dtype, opts: qs_batch_opts):
+    """Host-only plan of a batch: (passes, items) as lists of dicts, items in
+    ticket order (see qs_batch_plan in qsim.h)."""
+    arrs = [as_gates(g) for _, g in circuits]
+    cnt = len(arrs)
+    ns = np.ascontiguousarray([int(n) for n, _ in circuits], dtype=np.intc)
+    ptrs = (ctypes.c_void_p * cnt)(*[a.ctypes.data for a in arrs])
+    ngs = (ctypes.c_int64 * cnt)(*[len(a) for a in arrs])
+    npass, nitem = ctypes.c_int64(), ctypes.c_int64()
+    _chk(load().qs_batch_plan(cnt, ns.ctypes.data_as(_ip), ptrs, ngs, _dtype_code(dtype), ctypes.byref(opts),
+                              None, 0, ctypes.byref(npass), None, 0, ctypes.byref(nitem)))
+    P = (qs_batch_pass_info * max(1, npass.value))()
+    I = (qs_batch_item_info * max(1, nitem.value))()
+    _chk(load().qs_batch_plan(cnt, ns.ctypes.data_as(_ip), ptrs, ngs, _dtype_code(dtype), ctypes.byref(opts),
+                              P, npass.value, ctypes.byref(npass), I, nitem.value, ctypes.byref(nitem)))
+    passes = [dict(circuit=p.circuit, level=p.level, k_tile=p.k_tile, last=p.last, tiles=p.tiles)
+              for p in P[:npass.value]]
+    items = [dict(pass_=i.pass_, dep=i.dep, t0=i.t0, t1=i.t1, need=i.need) for i in I[:nitem.value]]
+    return passes, items
 
 
 def qs_batch_run(h: int) -> None:
@@ -588,26 +624,14 @@ class Program:
 class Batch:
     """Many circuits (list of (n, gates)) run by one persistent launch."""
 
-    def __init__(self, circuits, dtype="c64", solo_tiles=None, **opts):
+    def __init__(self, circuits, dtype="c64", **opts):
         self.ns = [int(n) for n, _ in circuits]
         self.count = len(self.ns)
         self.opts = dict(opts)
         self.h = qs_batch_create(circuits, dtype, make_batch_opts(**opts))
-        if solo_tiles is not None:  # else the library's default
-            try:
-                self.set_solo_tiles(solo_tiles)
-            except Exception:
-                self.close()
-                raise
 
     def run(self) -> "Batch":
         qs_batch_run(self.h)
-        return self
-
-    def set_solo_tiles(self, min_tiles: int) -> "Batch":
-        """Passes of at least min_tiles tiles (not a circuit's last) run as
-        launches of their own; 0: none."""
-        _chk(load().qs_batch_set_solo_tiles(self.h, int(min_tiles)))
         return self
 
     def results(self):
