@@ -63,13 +63,16 @@ def parse():
                          "subset of precision, batch, serve; empty: none)")
     ap.add_argument("--form-steps", type=int, default=1, help="timed steps of each form after its warm-up")
     ap.add_argument("--retune", action="store_true", help="batch: ignore the autotuner's cache")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch: skip the autotuner and use the options it chose on MI355X (k_tile 12, r 16, "
+                         "4 pinned, 3 workgroups per CU, 8 tiles per item)")
     ap.add_argument("--accuracy-requests", type=int, default=64,
                     help="serve: requests re-run alone in complex128 to state the served accuracy")
     ap.add_argument("--cpu-one-core-seconds", type=float, default=4.0,
                     help="oracle sample length with one thread (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
-    ap.add_argument("--rate-sweep", default="",
+    ap.add_argument("--rate-sweep", default="5,10,15",
                     help="serve: comma-separated lower arrival rates, each run with --sweep-requests requests after "
                          "the main trace (finds the load one GPU sustains)")
     ap.add_argument("--sweep-requests", type=int, default=60)
@@ -248,8 +251,11 @@ def batch_form(a):
     wl = batch_workload(count=256)
     circuits = [(n, g) for n, d, g in wl]
     t0 = time.perf_counter()
-    best, table = autotune.tune_batch(circuits, "c64", reps=2, refresh=a.retune,
-                                      log=lambda m: print("tune " + m, file=sys.stderr, flush=True))
+    if a.no_tune:
+        best, table = dict(k_tile=12, max_swaps=16, pinned=4, wg_per_cu=3, chunk=8, use_graph=1), []
+    else:
+        best, table = autotune.tune_batch(circuits, "c64", reps=2, refresh=a.retune,
+                                          log=lambda m: print("tune " + m, file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
     t1 = time.perf_counter()
     b = Q.Batch(circuits, "c64", **best)

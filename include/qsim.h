@@ -399,10 +399,15 @@ qs_status qs_server_fits(const qs_server *s, int n, int *fits);
  * QS_ERR_BUDGET when the budget or the slots are exhausted. */
 qs_status qs_server_admit(qs_server *s, const qs_program *p, void *state_buf, size_t buf_bytes,
                           const uint64_t *samples, int count, int64_t *request_id);
-/* Enqueue one step; *n_running receives the requests advanced. */
+/* Enqueue one step; *n_running receives the requests advanced.  Up to two
+ * steps may be in flight: the next step can be enqueued before the previous
+ * one is waited for (QS_ERR_STATE with two pending).  Requests admitted
+ * between two launches join the later one.  Large requests' passes run on
+ * up to three side streams forked from and joined back into the server's
+ * stream, concurrently with the step's shared launch. */
 qs_status qs_server_step_launch(qs_server *s, int *n_running);
-/* Wait for the last step; writes the ids of requests that completed in it
- * (up to cap) into ids and their number into *n_done. */
+/* Wait for the oldest step in flight; writes the ids of requests that
+ * completed in it (up to cap) into ids and their number into *n_done. */
 qs_status qs_server_step_wait(qs_server *s, int64_t *ids, int cap, int *n_done);
 /* Results of a completed request: z (host, n doubles) = <Z_q>, amps (host,
  * 2*count doubles, interleaved re, im) and *norm, all accumulated in FP64. */

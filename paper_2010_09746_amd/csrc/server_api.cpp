@@ -117,6 +117,18 @@ template <typename F> qs_status guard(F &&f)
 
 }  // namespace
 
+// One enqueued step: the requests whose last pass (and read-out) it runs and
+// the event recorded after its work.
+struct SStep {
+    std::vector<int64_t> finishing;
+    hipEvent_t ev = nullptr;
+    BatchItem *d_items = nullptr, *h_items = nullptr;  // this step's work items (device, pinned staging)
+    size_t items_cap = 0;
+};
+
+constexpr int MAX_STEPS_IN_FLIGHT = 2;
+constexpr int SIDE_STREAMS = 3;  // with the server's own stream: 4, the device's hardware queues
+
 struct qs_server {
     qs_dtype dt = QS_C64;
     qs_batch_opts opts{};
@@ -124,21 +136,22 @@ struct qs_server {
     size_t budget = 0, resident = 0;
     int max_slots = 0, max_samples = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
+    // large requests' passes of a step run on these, forked from and joined
+    // back into the server's stream
+    hipStream_t side[SIDE_STREAMS] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[SIDE_STREAMS] = {};
+    SStep steps[MAX_STEPS_IN_FLIGHT];
+    int step_head = 0, steps_pending = 0;  // oldest pending step, number pending
     char *d_bytes = nullptr;
     RangeAlloc bytes_alloc;
     BatchPass *d_passes = nullptr;
     RangeAlloc pass_alloc;
-    BatchItem *d_items = nullptr, *h_items = nullptr;
-    size_t items_cap = 0;
     double *d_zwork = nullptr;
     double *h_res = nullptr;  // pinned: max_slots slots of res_stride doubles
     size_t res_stride = 0;
     std::vector<int> free_slots;
     std::map<int64_t, SReq> reqs;
     std::vector<int64_t> active;  // admission order
-    std::vector<int64_t> finishing;
-    bool pending = false;
     int64_t next_id = 1;
     // a request whose pass has at least this many tiles runs it as a tile-pass
     // launch of its own (one workgroup per tile) inside the step; 0: never
@@ -151,36 +164,52 @@ void destroy_server(qs_server *s)
 {
     if (s->stream)
         (void)hipStreamSynchronize(s->stream);
-    if (s->ev)
-        (void)hipEventDestroy(s->ev);
-    void *dev[] = {s->d_bytes, s->d_passes, s->d_items, s->d_zwork};
+    for (auto &st : s->steps)
+        if (st.ev)
+            (void)hipEventDestroy(st.ev);
+    if (s->fork_ev)
+        (void)hipEventDestroy(s->fork_ev);
+    for (int i = 0; i < SIDE_STREAMS; ++i) {
+        if (s->join_ev[i])
+            (void)hipEventDestroy(s->join_ev[i]);
+        if (s->side[i]) {
+            (void)hipStreamSynchronize(s->side[i]);
+            (void)hipStreamDestroy(s->side[i]);
+        }
+    }
+    void *dev[] = {s->d_bytes, s->d_passes, s->d_zwork};
     for (void *p : dev)
         if (p)
             (void)hipFree(p);
-    if (s->h_items)
-        (void)hipHostFree(s->h_items);
+    for (auto &st : s->steps) {
+        if (st.d_items)
+            (void)hipFree(st.d_items);
+        if (st.h_items)
+            (void)hipHostFree(st.h_items);
+    }
     if (s->h_res)
         (void)hipHostFree(s->h_res);
     if (s->stream)
         (void)hipStreamDestroy(s->stream);
 }
 
-void ensure_items(qs_server *s, size_t need)
+// Grow a step's item buffers; the step's previous use has been waited for.
+void ensure_items(SStep &st, size_t need)
 {
-    if (need <= s->items_cap)
+    if (need <= st.items_cap)
         return;
-    size_t cap = std::max<size_t>(need, 2 * s->items_cap);
-    if (s->d_items)
-        hipchk(hipFree(s->d_items), "hipFree");
-    if (s->h_items)
-        hipchk(hipHostFree(s->h_items), "hipHostFree");
-    s->d_items = nullptr;
-    s->h_items = nullptr;
-    s->items_cap = 0;
-    hipchk(hipMalloc(&s->d_items, cap * sizeof(BatchItem)), "hipMalloc(items)");
-    hipchk(hipHostMalloc(reinterpret_cast<void **>(&s->h_items), cap * sizeof(BatchItem), hipHostMallocDefault),
+    size_t cap = std::max<size_t>(need, 2 * st.items_cap);
+    if (st.d_items)
+        hipchk(hipFree(st.d_items), "hipFree");
+    if (st.h_items)
+        hipchk(hipHostFree(st.h_items), "hipHostFree");
+    st.d_items = nullptr;
+    st.h_items = nullptr;
+    st.items_cap = 0;
+    hipchk(hipMalloc(&st.d_items, cap * sizeof(BatchItem)), "hipMalloc(items)");
+    hipchk(hipHostMalloc(reinterpret_cast<void **>(&st.h_items), cap * sizeof(BatchItem), hipHostMallocDefault),
            "hipHostMalloc(items)");
-    s->items_cap = cap;
+    st.items_cap = cap;
 }
 
 }  // namespace
@@ -209,7 +238,13 @@ qs_status qs_server_create(qs_dtype dt, const qs_batch_opts *opts, size_t hbm_bu
             s->max_slots = max_slots;
             s->max_samples = max_samples;
             hipchk(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
-            hipchk(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming), "hipEventCreate");
+            for (auto &st : s->steps)
+                hipchk(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming), "hipEventCreate");
+            hipchk(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming), "hipEventCreate");
+            for (int i = 0; i < SIDE_STREAMS; ++i) {
+                hipchk(hipStreamCreateWithFlags(&s->side[i], hipStreamNonBlocking), "hipStreamCreate");
+                hipchk(hipEventCreateWithFlags(&s->join_ev[i], hipEventDisableTiming), "hipEventCreate");
+            }
             hipchk(hipMalloc(&s->d_bytes, ARENA_BYTES), "hipMalloc(server arena)");
             s->bytes_alloc.init(ARENA_BYTES);
             hipchk(hipMalloc(&s->d_passes, PASS_RECORDS * sizeof(BatchPass)), "hipMalloc(server passes)");
@@ -225,7 +260,8 @@ qs_status qs_server_create(qs_dtype dt, const qs_batch_opts *opts, size_t hbm_bu
             hipchk(hipGetDevice(&dev), "hipGetDevice");
             hipchk(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
             s->grid = std::max(1, cus * std::max(1, opts->wg_per_cu));
-            ensure_items(s, 4096);
+            for (auto &st : s->steps)
+                ensure_items(st, 4096);
         } catch (...) {
             destroy_server(s);
             delete s;
@@ -240,7 +276,7 @@ qs_status qs_server_set_solo_tiles(qs_server *s, int64_t min_tiles)
     return guard([&] {
         if (!s || min_tiles < 0)
             fail(QS_ERR_ARG, "bad arguments");
-        if (s->pending)
+        if (s->steps_pending)
             fail(QS_ERR_STATE, "a step is in flight");
         s->solo_tiles = (uint64_t)min_tiles;
     });
@@ -366,8 +402,9 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
     return guard([&] {
         if (!s)
             fail(QS_ERR_ARG, "server is NULL");
-        if (s->pending)
-            fail(QS_ERR_STATE, "previous step not waited for");
+        if (s->steps_pending >= MAX_STEPS_IN_FLIGHT)
+            fail(QS_ERR_STATE, "two steps in flight: wait for the older one first");
+        SStep &step = s->steps[(s->step_head + s->steps_pending) % MAX_STEPS_IN_FLIGHT];
         const uint32_t chunk = (uint32_t)std::max(1, s->opts.chunk);
         size_t need = 0;
         for (int64_t id : s->active) {
@@ -375,10 +412,10 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
             if (r.cur < r.np)
                 need += ((1ull << (r.n - s->K)) + chunk - 1) / chunk;
         }
-        ensure_items(s, need + 1);
+        ensure_items(step, need + 1);
         size_t ni = 0;
         int running = 0;
-        s->finishing.clear();
+        step.finishing.clear();
         std::vector<const BatchPass *> solo;
         for (int64_t id : s->active) {
             SReq &r = s->reqs.at(id);
@@ -390,19 +427,28 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
                 solo.push_back(&r.passes[r.cur]);
             } else {
                 for (uint32_t t = 0; t < nt; t += chunk)
-                    s->h_items[ni++] = BatchItem{pi, t, std::min(nt, t + chunk), 0};
+                    step.h_items[ni++] = BatchItem{pi, t, std::min(nt, t + chunk), 0};
             }
             ++r.cur;
             ++running;
             if (r.cur == r.np)
-                s->finishing.push_back(id);
+                step.finishing.push_back(id);
+        }
+        // the large passes start with the shared launch: each request appears
+        // once in a step, so they are independent of it
+        const int ns = std::min<int>(SIDE_STREAMS, (int)solo.size());
+        if (ns) {
+            hipchk(hipEventRecord(s->fork_ev, s->stream), "hipEventRecord");
+            for (int i = 0; i < ns; ++i)
+                hipchk(hipStreamWaitEvent(s->side[i], s->fork_ev, 0), "hipStreamWaitEvent");
         }
         if (ni) {
-            hipchk(hipMemcpyAsync(s->d_items, s->h_items, ni * sizeof(BatchItem), hipMemcpyHostToDevice, s->stream),
+            hipchk(hipMemcpyAsync(step.d_items, step.h_items, ni * sizeof(BatchItem), hipMemcpyHostToDevice,
+                                  s->stream),
                    "hipMemcpyAsync(items)");
             BatchArgs a{};
             a.passes = s->d_passes;
-            a.items = s->d_items;
+            a.items = step.d_items;
             a.i0 = 0;
             a.i1 = (uint32_t)ni;
             a.partials = nullptr;
@@ -413,15 +459,24 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
                 launch_batch_f64(a, s->log_r, s->log_nt, grid, s->stream);
         }
         // large passes fill the device by themselves: one workgroup per tile
-        // (streaming loads and stores where whole lines move) instead of the
-        // shared persistent launch
-        for (const BatchPass *P : solo) {
-            if (s->dt == QS_C64)
-                launch_tile_f32(P->t, P->ntiles, s->log_r, s->log_nt, s->stream);
-            else
-                launch_tile_f64(P->t, P->ntiles, s->log_r, s->log_nt, s->stream);
+        // (streaming loads and stores where whole lines move), spread over
+        // the side streams so that one launch's tail overlaps the next one's
+        // start; the server's stream waits for them before the read-outs
+        if (ns) {
+            for (size_t i = 0; i < solo.size(); ++i) {
+                const BatchPass *P = solo[i];
+                hipStream_t st = s->side[i % ns];
+                if (s->dt == QS_C64)
+                    launch_tile_f32(P->t, P->ntiles, s->log_r, s->log_nt, st);
+                else
+                    launch_tile_f64(P->t, P->ntiles, s->log_r, s->log_nt, st);
+            }
+            for (int i = 0; i < ns; ++i) {
+                hipchk(hipEventRecord(s->join_ev[i], s->side[i]), "hipEventRecord");
+                hipchk(hipStreamWaitEvent(s->stream, s->join_ev[i], 0), "hipStreamWaitEvent");
+            }
         }
-        for (int64_t id : s->finishing) {
+        for (int64_t id : step.finishing) {
             SReq &r = s->reqs.at(id);
             double *out = reinterpret_cast<double *>(s->d_bytes + r.res_off);
             launch_zsum(r.state, s->dt, r.n, s->d_zwork, out, s->stream);
@@ -432,8 +487,8 @@ qs_status qs_server_step_launch(qs_server *s, int *n_running)
                                   s->stream),
                    "hipMemcpyAsync(results)");
         }
-        hipchk(hipEventRecord(s->ev, s->stream), "hipEventRecord");
-        s->pending = true;
+        hipchk(hipEventRecord(step.ev, s->stream), "hipEventRecord");
+        ++s->steps_pending;
         if (n_running)
             *n_running = running;
     });
@@ -445,10 +500,12 @@ qs_status qs_server_step_wait(qs_server *s, int64_t *ids, int cap, int *n_done)
         if (!s)
             fail(QS_ERR_ARG, "server is NULL");
         int w = 0;
-        if (s->pending) {
-            hipchk(hipEventSynchronize(s->ev), "hipEventSynchronize");
-            s->pending = false;
-            for (int64_t id : s->finishing) {
+        if (s->steps_pending > 0) {
+            SStep &step = s->steps[s->step_head];
+            hipchk(hipEventSynchronize(step.ev), "hipEventSynchronize");
+            s->step_head = (s->step_head + 1) % MAX_STEPS_IN_FLIGHT;
+            --s->steps_pending;
+            for (int64_t id : step.finishing) {
                 SReq &r = s->reqs.at(id);
                 const double *h = s->h_res + (size_t)r.slot * s->res_stride;
                 r.res.assign(h, h + r.res_len / sizeof(double));
@@ -460,7 +517,7 @@ qs_status qs_server_step_wait(qs_server *s, int64_t *ids, int cap, int *n_done)
                     ids[w] = id;
                 ++w;
             }
-            s->finishing.clear();
+            step.finishing.clear();
         }
         if (n_done)
             *n_done = w;

@@ -2,12 +2,13 @@
 
 Requests (circuits with their arrival times) are compiled on host threads as
 they arrive, admitted in arrival order whenever the HBM budget and a slot
-allow, and kept resident on the device.  Every iteration of the loop is one
-step of the native server (``qs_server_step_launch`` / ``_wait``): a single
-launch that runs the next tile pass of every resident request, so the work of
-requests that arrived at different times overlaps on the device; a request
-leaves after its last pass, with <Z_q> for every qubit and its sampled
-amplitudes (FP64 accumulation) copied back in the same step.
+allow, and kept resident on the device.  Each step of the native server
+(``qs_server_step_launch`` / ``_wait``) runs the next tile pass of every
+resident request, so the work of requests that arrived at different times
+overlaps on the device; two steps are kept in flight, so the host collects
+and admits while the device works.  A request leaves after its last pass,
+with <Z_q> for every qubit and its sampled amplitudes (FP64 accumulation)
+copied back in the same step.
 
 State buffers come from PyTorch's allocator; compiled tables live in the
 server's own device arena.
@@ -65,13 +66,17 @@ class Server:
     def serve(self, requests, realtime=True, log=None):
         """requests: dicts with id, arrival (s), n, gates, samples.  Returns
         (results {id: dict(z, amps, norm)}, records {id: dict(arrival, admit,
-        done, n, gates)})."""
+        done, n, gates)}).  Up to two steps are in flight: the next step is
+        enqueued before the previous one is waited for, so the device has
+        queued work while the host collects results and admits requests."""
         reqs = sorted(requests, key=lambda r: r["arrival"])
         total = len(reqs)
         waiting = collections.deque()      # arrived, not admitted: (req, future)
-        running = {}                       # server id -> (req, buffer, program)
+        running = {}                       # server id -> (req, buffer, program, samples)
+        left = {}                          # server id -> passes not yet enqueued
         results, rec = {}, {}
         nxt = 0
+        inflight = 0
         t0 = time.perf_counter()
         max_resident = 0
         steps = 0
@@ -93,15 +98,33 @@ class Server:
                     torch.cuda.empty_cache()
                     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
                 smp = np.asarray(r["samples"][: self.max_samples], dtype=np.uint64)
-                sid = Q.qs_server_admit(self.h, prog.h, buf.data_ptr(), nbytes, smp)
+                try:
+                    sid = Q.qs_server_admit(self.h, prog.h, buf.data_ptr(), nbytes, smp)
+                except Q.QsimError as e:
+                    # QS_ERR_BUDGET with requests resident: the server's table
+                    # arena is full until one of them leaves
+                    if e.code != -3 or not running:
+                        raise
+                    del buf
+                    waiting.appendleft((r, fut))
+                    break
                 running[sid] = (r, buf, prog, len(smp))
+                left[sid] = max(1, prog.stats()["n_tile_passes"])
                 rec[r["id"]]["admit"] = time.perf_counter() - t0
             max_resident = max(max_resident, len(running))
-            if running:
+            if inflight < 2 and any(v > 0 for v in left.values()):
                 Q.qs_server_step_launch(self.h)
+                for sid in left:
+                    left[sid] = max(0, left[sid] - 1)
+                inflight += 1
                 steps += 1
+                if inflight < 2:
+                    continue  # enqueue the next step before waiting for this one
+            if inflight:
+                inflight -= 1
                 for sid in Q.qs_server_step_wait(self.h):
                     r, buf, prog, cnt = running.pop(sid)
+                    left.pop(sid, None)
                     z, amps, nrm = Q.qs_server_result(self.h, sid, r["n"], cnt)
                     Q.qs_server_release(self.h, sid)
                     del buf
