@@ -100,13 +100,17 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *              (0 = chosen by the library).
  *   flags      QS_OPT_FULL_MATRICES: every one-qubit gate of a tile pass is
  *              applied as its whole 2x2 matrix.  Without it (0, the
- *              default) an uncontrolled gate M on qubit q is factored as
- *              M = e^{i phi} diag(1, e^{i theta}) W, W = [[a, -conj(b)],
- *              [b, a]] with a real (12 real multiply-adds per amplitude pair
- *              instead of 16); diag(1, e^{i theta}) is kept pending on q
- *              and absorbed by q's next one-qubit gate, or applied before an
- *              operation that acts on q non-diagonally, and the scalar is
- *              folded into the last gate.  Same result up to rounding.
+ *              default) an uncontrolled gate M on qubit q (with q's pending
+ *              diagonal absorbed) is factored as
+ *              M = M00 diag(1, z) [[1, 0], [q, 1]] [[1, p], [0, 1]]
+ *              (or the same for M X, after an exchange that relabels
+ *              register slots, when |M01| > |M00|): two in-place shears,
+ *              8 real multiply-adds per amplitude pair instead of 16.
+ *              diag(1, z) is kept pending on q and absorbed by q's next
+ *              one-qubit gate, or applied before an operation that acts on
+ *              q non-diagonally; M00 goes into one scalar that the next
+ *              gate applied whole takes, and the last gate of each qubit
+ *              is applied whole.  Same result up to rounding.
  */
 enum { QS_OPT_FULL_MATRICES = 1 };
 typedef struct {
@@ -195,8 +199,8 @@ qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
  *   QS_OPC_PLAIN_*     one-gate launches by gate kind
  *   QS_OPC_MOVE        data-movement launches, QS_OPC_MOVE_FRACTION the sum
  *                      of the fractions of amplitudes they move
- *   QS_OPC_W           one-qubit updates in the reduced form W (see flags)
- *   QS_OPC_PHASE       pending phases applied on their own (see flags)
+ *   QS_OPC_SHEAR       one-qubit updates as two shears (see flags)
+ *   QS_OPC_PHASE       pending diagonals applied on their own (see flags)
  * Writes min(cap, QS_OPC_COUNT) entries. */
 enum {
     QS_OPC_TILE_PASS = 0,
@@ -214,8 +218,8 @@ enum {
     QS_OPC_PLAIN_CZ = 12,
     QS_OPC_MOVE = 13,
     QS_OPC_MOVE_FRACTION = 14,
-    QS_OPC_W = 15,         /* reduced one-qubit update W */
-    QS_OPC_PHASE = 16,     /* pending phase applied on its own */
+    QS_OPC_SHEAR = 15,     /* one-qubit update as two shears */
+    QS_OPC_PHASE = 16,     /* pending diagonal applied on its own */
     QS_OPC_COUNT = 17
 };
 qs_status qs_program_op_counts(const qs_program *p, double *out, int cap);

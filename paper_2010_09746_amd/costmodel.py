@@ -34,7 +34,7 @@ from . import qsim as Q
 
 from workloads import KIND_CU, KIND_CX, KIND_CZ, KIND_U, haar_u2, make_gates, phase
 
-TILE_CLASSES = ["tile_pass", "u", "w", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch"]
+TILE_CLASSES = ["tile_pass", "u", "shear", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch"]
 # compile options of calibration circuits that need them: "u" measures whole
 # 2x2 updates, so its circuit keeps every matrix whole
 CAL_OPTS = {"u": dict(full_matrices=True)}
@@ -67,8 +67,8 @@ def calibration_circuits(n: int, k: int, log_r: int, seed: int = 20100946 + 9) -
     c = {
         "base": [U(0)],
         "u": [U(q % R) for q in range(N + 1)],
-        # the same gates in the reduced form (all but each qubit's last)
-        "w": [U(q % R) for q in range(N + 1)],
+        # the same gates as shears (all but each qubit's last)
+        "shear": [U(q % R) for q in range(N + 1)],
         "u_ctrl": [U(0)] + [(KIND_CU, (q + 1) % R, q % R, haar_u2(rng)) for q in range(N)] if R > 1 else None,
         "x_reg": [U(0)] + [(KIND_CX, (q + 1) % R, q % R, None) for q in range(N)] if R > 1 else None,
         "x_lane": [U(0)] + [(KIND_CX, R + 1, q % R, None) for q in range(N)],

@@ -705,8 +705,8 @@ qs_status qs_program_op_counts(const qs_program *p, double *out, int cap)
                     case OP_NEG:
                         c[QS_OPC_NEG] += w;
                         break;
-                    case OP_W:
-                        c[QS_OPC_W] += w;
+                    case OP_SHEAR:
+                        c[QS_OPC_SHEAR] += w;
                         break;
                     case OP_PHASE:
                         c[QS_OPC_PHASE] += w;

@@ -437,121 +437,102 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 // ---------------------------------------------------------------------------
 // Pending one-qubit phases (lowering only; the pass is unchanged).
 //
-// Every unitary 2x2 matrix M factors as M = e^{i phi} diag(1, e^{i theta}) W
-// with W = [[a, -conj(b)], [b, a]] and a >= 0 real: with V = e^{-i phi} M in
-// SU(2), V = [[alpha, -conj(beta)], [beta, conj(alpha)]], psi = arg(alpha),
-// a = |alpha|, b = beta e^{i psi}, theta = -2 psi, and the scalar phase
-// e^{i (phi + psi)}.  W updates an amplitude pair with 12 real multiply-adds
-// instead of the 16 of a general complex 2x2.
+// Every invertible 2x2 matrix M with M00 != 0 factors as
+//   M = M00 diag(1, z) L(q) U(p),  U(p) = [[1, p], [0, 1]], L(q) = [[1, 0], [q, 1]],
+// with p = M01 / M00, q = M10 M00 / det M and z = det M / M00^2 (multiply
+// out: the product is [[M00, M01], [M10, M11]]).  The two shears update an
+// amplitude pair (x, y) in place, x += p y and then y += q x, with 8 real
+// multiply-adds instead of the 16 of a general complex 2x2, and need no
+// temporary.  When |M01| > |M00| the same is done for M X = [[M01, M00],
+// [M11, M10]] (det M X = -det M) and an exchange X on the qubit runs first
+// (flagged on the op: an uncontrolled exchange on a register slot is a
+// relabelling of slots and moves no data).  Pivoting on the larger entry of the first row keeps
+// |p| <= 1.
 //
-// The lowering applies the W of each uncontrolled one-qubit gate and keeps
-// diag(1, f) pending on the gate's qubit q: the stored state equals the true
-// state up to the product of the pending phases and one scalar.  A pending
-// phase commutes with every operation that acts diagonally on q (CZ, a
-// control on q), so it stays pending through them.  The next one-qubit gate on
-// q absorbs it into its own matrix (host arithmetic, no device work); an
+// The lowering applies the shears of each uncontrolled one-qubit gate in a
+// tile pass and keeps diag(1, z) pending on the gate's qubit q, and the factor
+// M00 in one scalar for the whole state: the stored state equals the true
+// state with the pending diagonals and the scalar divided out.  A pending
+// diagonal commutes with every operation that acts diagonally on q (CZ, a
+// control on q), so it stays pending through them.  The next one-qubit gate
+// on q absorbs it into its own matrix (host arithmetic, no device work); an
 // operation that acts on q non-diagonally otherwise (the target of a CNOT or
-// of a controlled gate) needs it applied first: it is folded into the W that
-// left it when that W is still in the segment being scheduled (the op becomes
-// the general 2x2 D W), else applied as a phase on the qubit.  The last
-// one-qubit gate of each qubit is applied whole, with its qubit's pending
-// phase absorbed, and the last of all also carries the accumulated scalar, so
-// the state is exact (up to rounding) when the program ends.
+// of a controlled gate) needs it applied first, as a multiplication of the
+// amplitudes whose bit q is 1 (OP_PHASE; with the shears 12 multiply-adds,
+// still fewer than a general 2x2).  The last one-qubit gate of each qubit is
+// applied whole with its qubit's pending diagonal absorbed, and a gate
+// applied whole also takes the scalar (it touches every amplitude), so the
+// state is exact (up to rounding) when the program ends.  The stored
+// amplitudes stay within a bounded factor of the true ones: a gate is applied
+// whole instead when its new pending |z| would leave [1/4, 4], the scalar's
+// magnitude [2^-8, 2^8], or |q| exceed 16, so that complex64 states keep at
+// least 2^-(2n+8) of their magnitude range.
 struct PhaseFrame {
     using cd = std::complex<double>;
+    static constexpr double Z_LO = 0.25, Z_HI = 4.0, S_LO = 1.0 / 256.0, S_HI = 256.0, Q_MAX = 16.0;
     bool on = false;
-    std::vector<cd> f;            // pending diag(1, f[q]) per logical qubit
-    std::vector<int64_t> w_op;    // op index of the W that left f[q], -1 if none
+    std::vector<cd> z;            // pending diag(1, z[q]) per logical qubit
     std::vector<int64_t> u_left;  // non-diagonal one-qubit gates of q not yet lowered
-    int64_t u_total = 0;          // the same over all qubits
-    cd scalar{1.0, 0.0};          // accumulated e^{i (phi + psi)}
-    int64_t seg_begin = 0;        // ops from here on belong to the segment being scheduled
+    cd scalar{1.0, 0.0};          // accumulated product of the pivots
 
     void init(const qs_gate *g, const std::vector<GateInfo> &gi, int64_t ng, int n)
     {
-        f.assign(n, cd(1.0, 0.0));
-        w_op.assign(n, -1);
+        z.assign(n, cd(1.0, 0.0));
         u_left.assign(n, 0);
-        u_total = 0;
         scalar = cd(1.0, 0.0);
         for (int64_t v = 0; v < ng; ++v)
-            if (g[v].kind == QS_GATE_U && gi[v].act0 != ACT_Z) {
+            if (g[v].kind == QS_GATE_U && gi[v].act0 != ACT_Z)
                 ++u_left[g[v].q0];
-                ++u_total;
-            }
     }
     static cd at(const double *m, int i) { return cd(m[2 * i], m[2 * i + 1]); }
-    static void put(double *m, int i, cd z)
+    static void put(double *m, int i, cd c)
     {
-        m[2 * i] = z.real();
-        m[2 * i + 1] = z.imag();
-    }
-    static bool unitary(const cd *M)
-    {
-        const cd a = std::conj(M[0]) * M[0] + std::conj(M[2]) * M[2];
-        const cd b = std::conj(M[1]) * M[1] + std::conj(M[3]) * M[3];
-        const cd c = std::conj(M[0]) * M[1] + std::conj(M[2]) * M[3];
-        return std::abs(a - 1.0) < 1e-13 && std::abs(b - 1.0) < 1e-13 && std::abs(c) < 1e-13;
+        m[2 * i] = c.real();
+        m[2 * i + 1] = c.imag();
     }
     // Lower the uncontrolled one-qubit gate u on logical qubit q: writes the
-    // op's kind and matrix fields (OP_W: m[0] = a, m[1..2] = b; OP_U: the
-    // whole matrix) and updates the pending phase of q.
-    void one_qubit(int q, const double *u, int64_t op_index, int32_t *kind, double *m)
+    // op's kind and matrix fields (OP_SHEAR: m[0..1] = p, m[2..3] = q; OP_U:
+    // the whole matrix) and *flip, true when an uncontrolled exchange on q
+    // must run just before the op; updates the pending diagonal of q.
+    void one_qubit(int q, const double *u, int32_t *kind, double *m, bool *flip)
     {
-        cd M[4] = {at(u, 0), at(u, 1) * f[q], at(u, 2), at(u, 3) * f[q]};
-        --u_left[q];
-        --u_total;
-        if (u_left[q] == 0 || !unitary(M)) {
-            if (u_total == 0) {
-                for (cd &x : M)
-                    x *= scalar;
-                scalar = cd(1.0, 0.0);
-            }
-            *kind = OP_U;
-            for (int i = 0; i < 4; ++i)
-                put(m, i, M[i]);
-            f[q] = cd(1.0, 0.0);
-            w_op[q] = -1;
-            return;
-        }
-        const cd det = M[0] * M[3] - M[1] * M[2];
-        const double phi = 0.5 * std::arg(det);
-        const cd alpha = M[0] * std::polar(1.0, -phi), beta = M[2] * std::polar(1.0, -phi);
-        const double a = std::abs(alpha), psi = a > 0.0 ? std::arg(alpha) : 0.0;
-        const cd b = beta * std::polar(1.0, psi);
-        *kind = OP_W;
+        const cd M[4] = {at(u, 0), at(u, 1) * z[q], at(u, 2), at(u, 3) * z[q]};
+        *flip = false;
         std::memset(m, 0, 8 * sizeof(double));
-        m[0] = a;
-        m[1] = b.real();
-        m[2] = b.imag();
-        f[q] = std::polar(1.0, -2.0 * psi);
-        scalar *= std::polar(1.0, phi + psi);
-        scalar /= std::abs(scalar);
-        w_op[q] = op_index;
+        if (--u_left[q] > 0) {
+            const cd det = M[0] * M[3] - M[1] * M[2];
+            const bool x = std::abs(M[1]) > std::abs(M[0]);
+            const cd piv = x ? M[1] : M[0];
+            // with the exchange: M X = [[M01, M00], [M11, M10]], det M X = -det M
+            const cd p = (x ? M[0] : M[1]) / piv, qq = x ? -M[3] * piv / det : M[2] * piv / det;
+            const cd zn = x ? -det / (piv * piv) : det / (piv * piv), sn = scalar * piv;
+            const double az = std::abs(zn), as = std::abs(sn);
+            if (std::abs(det) > 0.0 && az >= Z_LO && az <= Z_HI && as >= S_LO && as <= S_HI &&
+                std::abs(qq) <= Q_MAX) {
+                *kind = OP_SHEAR;
+                *flip = x;
+                put(m, 0, p);
+                put(m, 1, qq);
+                z[q] = zn;
+                scalar = sn;
+                return;
+            }
+        }
+        *kind = OP_U;
+        for (int i = 0; i < 4; ++i)
+            put(m, i, M[i] * scalar);
+        scalar = cd(1.0, 0.0);
+        z[q] = cd(1.0, 0.0);
     }
     // Before an operation that acts on q non-diagonally other than a
-    // one-qubit gate: the pending phase must be applied.  Returns true when
-    // the caller must emit OP_PHASE with f (the W that left it is final), and
-    // writes f to *out; folds it into that W otherwise.
-    bool settle(int q, std::vector<TileOp> &ops, cd *out)
+    // one-qubit gate: returns true, with the pending factor in *out, when the
+    // caller must apply diag(1, *out) on q first.
+    bool settle(int q, cd *out)
     {
-        const cd ph = f[q];
-        const int64_t w = w_op[q];
-        f[q] = cd(1.0, 0.0);
-        w_op[q] = -1;
+        const cd ph = z[q];
+        z[q] = cd(1.0, 0.0);
         if (ph == cd(1.0, 0.0))
             return false;
-        if (w >= seg_begin && w >= 0 && w < (int64_t)ops.size() && ops[w].kind == OP_W) {
-            TileOp &o = ops[w];
-            const double a = o.m[0];
-            const cd b(o.m[1], o.m[2]);
-            o.kind = OP_U;
-            put(o.m, 0, cd(a, 0.0));
-            put(o.m, 1, -std::conj(b));
-            put(o.m, 2, b * ph);
-            put(o.m, 3, a * ph);
-            return false;
-        }
         *out = ph;
         return true;
     }
@@ -564,7 +545,6 @@ constexpr int LOOKAHEAD_TARGETS = 8;
 int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::vector<GateInfo> &gi,
                      int k, int log_r, std::vector<TileOp> &ops, PhaseFrame &pf)
 {
-    pf.seg_begin = (int64_t)ops.size();
     const int cnt = (int)lg.size();
     // in-segment predecessors
     std::vector<std::vector<int>> pred(cnt);
@@ -640,12 +620,14 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
                 if (pf.on) {
                     const qs_gate &src = g[lg[v].src];
                     if (src.kind == QS_GATE_U && op.kind == OP_U) {
-                        pf.one_qubit(src.q0, src.u, (int64_t)ops.size(), &op.kind, op.m);
+                        bool flip = false;
+                        pf.one_qubit(src.q0, src.u, &op.kind, op.m, &flip);
+                        op.tlane = flip ? 1u : 0u;
                     } else if (needs_reg(v)) {
                         // X-type target of a CNOT, or the target of a
-                        // controlled 2x2: the pending phase goes first
+                        // controlled 2x2: the pending diagonal goes first
                         std::complex<double> ph;
-                        if (pf.settle(src.q1, ops, &ph)) {
+                        if (pf.settle(src.q1, &ph)) {
                             TileOp po{};
                             po.kind = OP_PHASE;
                             po.slot = slot;
@@ -886,17 +868,15 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                 // one launch of the whole matrix with the pending phase absorbed
                 int32_t kind = OP_U;
                 double m[8];
+                bool flip = false;
                 const int64_t left = pf.u_left[g[v].q0];
                 pf.u_left[g[v].q0] = 1;  // forces the whole-matrix form
-                pf.one_qubit(g[v].q0, g[v].u, -1, &kind, m);
+                pf.one_qubit(g[v].q0, g[v].u, &kind, m, &flip);
                 pf.u_left[g[v].q0] = left - 1;
                 std::memcpy(L.gate.u, m, sizeof m);
             } else if ((g[v].kind == QS_GATE_CX || g[v].kind == QS_GATE_CU) && gi[v].act1 != ACT_Z) {
                 std::complex<double> ph;
-                std::vector<TileOp> none;
-                const int64_t sb = pf.seg_begin;
-                pf.seg_begin = 0;  // no fusible op here: a launch of its own
-                if (pf.settle(g[v].q1, none, &ph)) {
+                if (pf.settle(g[v].q1, &ph)) {
                     Launch D;
                     D.type = L_PLAIN;
                     D.gate = qs_gate{};
@@ -909,7 +889,6 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                     p.launches.push_back(D);
                     ++p.stats.n_plain;
                 }
-                pf.seg_begin = sb;
             }
         }
         p.launches.push_back(L);

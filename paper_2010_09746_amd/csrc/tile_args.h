@@ -15,8 +15,9 @@ enum TileOpKind : int32_t {
     OP_DIAG = 2,   // multiply by d0 (m[0..1]) / d1 (m[2..3]) selected by the target bit
     OP_NEG = 3,    // negate where every control bit is 1
     OP_REMAP = 4,  // move amplitudes through LDS to a new register layout
-    OP_W = 5,      // [[a, -conj(b)], [b, a]] on register slot `slot`: a = m[0], b = (m[1], m[2]);
-                   // no controls
+    OP_SHEAR = 5,  // on the pair (x, y) of register slot `slot`: x += p y, then y += q x, with
+                   // p = (m[0], m[1]) and q = (m[2], m[3]); tlane != 0: exchange x and y
+                   // first (a relabelling); no controls
     OP_PHASE = 6,  // multiply where the bit of register slot `slot` is 1 by (m[0], m[1]); no
                    // controls
 };

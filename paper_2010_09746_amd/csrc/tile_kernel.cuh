@@ -162,66 +162,43 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
         }
     }
 
-    // W = [[a, -conj(b)], [b, a]] (a real) on one pair, in place: 12 real
-    // multiply-adds.  x' = a x - conj(b) y and y' = b x + a y; the partial
-    // sums read only the other element of the pair, and each output's last
-    // multiply-add reads its own register.  In FP64 the sequence is written
-    // out as instructions: compiled from the expressions, the register
-    // allocator kept the old values of whole pairs alive and the tile kernel
-    // needed 149 VGPRs (3 wavefronts per SIMD) instead of 117 (4).
-    static __device__ __forceinline__ void wpair(C &x, C &y, R a, R br, R bi)
+    // Two shears on one pair, in place: x += p y, then y += q x (with the new
+    // x).  8 real multiply-adds, each reading the register it writes, so no
+    // old value has to stay alive.
+    static __device__ __forceinline__ void spair(C &x, C &y, R pr, R pi, R qr, R qi)
     {
-        if constexpr (sizeof(R) == 8) {
-            double p0, p1, p2, p3;
-            __asm__("v_mul_f64 %[p0], %[yi], -%[bi]\n\t"
-                    "v_mul_f64 %[p1], %[yr], %[bi]\n\t"
-                    "v_mul_f64 %[p2], %[xi], -%[bi]\n\t"
-                    "v_mul_f64 %[p3], %[xr], %[bi]\n\t"
-                    "v_fma_f64 %[p0], -%[br], %[yr], %[p0]\n\t"
-                    "v_fma_f64 %[p1], -%[br], %[yi], %[p1]\n\t"
-                    "v_fma_f64 %[p2], %[br], %[xr], %[p2]\n\t"
-                    "v_fma_f64 %[p3], %[br], %[xi], %[p3]\n\t"
-                    "v_fma_f64 %[xr], %[a], %[xr], %[p0]\n\t"
-                    "v_fma_f64 %[xi], %[a], %[xi], %[p1]\n\t"
-                    "v_fma_f64 %[yr], %[a], %[yr], %[p2]\n\t"
-                    "v_fma_f64 %[yi], %[a], %[yi], %[p3]"
-                    : [xr] "+v"(x.x), [xi] "+v"(x.y), [yr] "+v"(y.x), [yi] "+v"(y.y), [p0] "=&v"(p0),
-                      [p1] "=&v"(p1), [p2] "=&v"(p2), [p3] "=&v"(p3)
-                    : [a] "s"(a), [br] "s"(br), [bi] "s"(bi));
-            return;
-        }
-        R p0 = -bi * y.y, p1 = bi * y.x, p2 = -bi * x.y, p3 = bi * x.x;
-        p0 = fmadd(-br, y.x, p0);
-        p1 = fmadd(-br, y.y, p1);
-        p2 = fmadd(br, x.x, p2);
-        p3 = fmadd(br, x.y, p3);
-        x.x = fmadd(a, x.x, p0);
-        x.y = fmadd(a, x.y, p1);
-        y.x = fmadd(a, y.x, p2);
-        y.y = fmadd(a, y.y, p3);
+        x.x = fmadd(pr, y.x, x.x);
+        x.y = fmadd(pr, y.y, x.y);
+        x.x = fmadd(-pi, y.y, x.x);
+        x.y = fmadd(pi, y.x, x.y);
+        y.x = fmadd(qr, x.x, y.x);
+        y.y = fmadd(qr, x.y, y.y);
+        y.x = fmadd(-qi, x.y, y.x);
+        y.y = fmadd(qi, x.x, y.y);
     }
-    // W on slot S, every pair.  With SW the slot's pattern bit is flipped.
-    template <int S, bool SW> static __device__ __forceinline__ void wfly(C (&v)[NR], R a, R br, R bi)
+    // the shears on slot S, every pair.  With SW the slot's pattern bit is
+    // flipped (the upper slot of a pair holds pattern bit 0).
+    template <int S, bool SW> static __device__ __forceinline__ void sfly(C (&v)[NR], R pr, R pi, R qr, R qi)
     {
 #pragma unroll
         for (int jj = 0; jj < NR / 2; ++jj) {
             const int j = pair_lo<S>(jj), j1 = j | (1 << S);
             if (SW)
-                wpair(v[j1], v[j], a, br, bi);
+                spair(v[j1], v[j], pr, pi, qr, qi);
             else
-                wpair(v[j], v[j1], a, br, bi);
+                spair(v[j], v[j1], pr, pi, qr, qi);
         }
     }
     template <int S = 0>
-    static __device__ __forceinline__ void dispatch_w(int slot, uint32_t sw, C (&v)[NR], R a, R br, R bi)
+    static __device__ __forceinline__ void dispatch_shear(int slot, uint32_t sw, C (&v)[NR], R pr, R pi, R qr, R qi)
     {
         if (slot == S || S == LOG_R - 1) {
             if (sw)
-                wfly<S, true>(v, a, br, bi);
+                sfly<S, true>(v, pr, pi, qr, qi);
             else
-                wfly<S, false>(v, a, br, bi);
+                sfly<S, false>(v, pr, pi, qr, qi);
         } else if constexpr (S + 1 < LOG_R) {
-            dispatch_w<S + 1>(slot, sw, v, a, br, bi);
+            dispatch_shear<S + 1>(slot, sw, v, pr, pi, qr, qi);
         }
     }
 
@@ -560,8 +537,10 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
                     const uint32_t rv = rm & ~fl;
                     const bool lp = (tbase & lm) == lm;
                     const int slot = cur.slot;
-                    if (kind == OP_W) {
-                        dispatch_w(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1], (R)cur.m[2]);
+                    if (kind == OP_SHEAR) {
+                        fl ^= cur.tlane ? 1u << slot : 0u;
+                        dispatch_shear(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1], (R)cur.m[2],
+                                       (R)cur.m[3]);
                     } else if (kind == OP_PHASE) {
                         dispatch_phase(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1]);
                     } else if (kind == OP_U) {

@@ -39,16 +39,17 @@ def test_noalloc_limit_agrees_with_header():
 
 def test_reduced_one_qubit_form_counts():
     """By default uncontrolled one-qubit gates of tile passes are lowered to
-    the reduced update W (all but each qubit's last); with full_matrices every
-    one is a whole 2x2 and no pending phase is applied on its own."""
+    two shears (all but each qubit's last and the few whose pending factors
+    would leave their bounds); with full_matrices every one is a whole 2x2
+    and no pending diagonal is applied on its own."""
     g = config_circuit(2, n=20, layers=10)
     a = Q.Program(g, 20, "c128", form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=3).op_counts()
     b = Q.Program(g, 20, "c128", form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=3,
                   full_matrices=True).op_counts()
     n_u = int(sum(1 for k in g["kind"] if k == KIND_U))
-    assert b["u"] == n_u and b["w"] == 0 and b["phase"] == 0
-    # every one-qubit gate is either W or whole; the last one of each qubit is whole
-    assert a["w"] + a["u"] == n_u and a["u"] >= 20 and a["w"] > a["u"]
+    assert b["u"] == n_u and b["shear"] == 0 and b["phase"] == 0
+    # every one-qubit gate is either two shears or whole; the last one of each qubit is whole
+    assert a["shear"] + a["u"] == n_u and a["u"] >= 20 and a["shear"] > 4 * a["u"]
 
 
 def test_gate_record_layout():

@@ -1,11 +1,13 @@
-"""The reduced one-qubit update (each uncontrolled gate as e^{i phi}
-diag(1, e^{i theta}) W with the phases kept pending on the qubit) against the
-whole-matrix form and the oracle, on every path that has to settle a pending
-phase: CNOT and controlled-gate targets inside a pass, targets whose W ended
-an earlier pass, gates run as launches of their own (fusion without the pass,
-and the fallback of Algorithm 1 when no exchange is allowed), non-unitary
-matrices (applied whole), and the last gate of each qubit (which carries the
-accumulated scalar)."""
+"""The reduced one-qubit update (each uncontrolled gate M of a tile pass as
+M00 diag(1, z) L(q) U(p), two in-place shears, with diag(1, z) kept pending
+on the qubit and M00 in one scalar) against the whole-matrix form and the
+oracle, on every path that has to settle a pending diagonal: CNOT and
+controlled-gate targets inside a pass, targets whose shears ended an earlier
+pass, gates run as launches of their own (fusion without the pass, and the
+fallback of Algorithm 1 when no exchange is allowed), gates whose larger
+first-row entry is off the diagonal (an exchange first), singular and
+non-unitary matrices, long programs whose scalar has to be taken by a whole
+gate, and the last gate of each qubit."""
 
 import sys
 
@@ -13,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from workloads import KIND_CU, KIND_U, haar_u2, layered_circuit, make_gates, mixed_circuit
+from workloads import KIND_CU, KIND_CX, KIND_U, haar_u2, layered_circuit, make_gates, mixed_circuit
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +54,7 @@ def test_reduced_equals_whole_matrices_and_oracle(dt, k, r, pinned, perm_exec):
     Pf = Q.Program(g, n, dt, full_matrices=True, **opts)
     cf = Pf.op_counts()
     Pf.close()
-    assert c["w"] > 0 and cf["w"] == 0 and cf["phase"] == 0
+    assert c["shear"] > 0 and cf["shear"] == 0 and cf["phase"] == 0
     ref = O.run(g, n)
     a = _run(g, n, dt, **opts)
     b = _run(g, n, dt, full_matrices=True, **opts)
@@ -62,8 +64,7 @@ def test_reduced_equals_whole_matrices_and_oracle(dt, k, r, pinned, perm_exec):
 
 def test_pending_phase_settled_across_passes():
     """Small tiles and bundles of one exchange: many CNOT targets meet a
-    pending phase left by a W of an earlier pass (applied as a phase of its
-    own)."""
+    pending diagonal left by shears of an earlier pass (applied on its own)."""
     n = 14
     _say("pending phases across passes")
     g = layered_circuit(n, 30, seed=77)
@@ -78,7 +79,7 @@ def test_pending_phase_settled_across_passes():
 def test_launches_of_their_own_settle_phases(r, pinned):
     """r = 0 (fusion without the pass) and pinned = k (no exchange allowed, so
     Algorithm 1's fallback applies non-local gates as launches of their own):
-    one-qubit launches absorb the pending phase, CNOT and controlled-gate
+    one-qubit launches absorb the pending diagonal, CNOT and controlled-gate
     launches get it applied first."""
     n, k = 13, 9
     _say(f"own launches r={r} pinned={pinned}")
@@ -91,21 +92,58 @@ def test_launches_of_their_own_settle_phases(r, pinned):
     assert np.abs(_run(g, n, "c128", **opts) - O.run(g, n)).max() <= 1e-12
 
 
-def test_non_unitary_matrices_applied_whole():
-    """A matrix that is not unitary cannot be factored; it is applied whole
-    (with the pending phase absorbed) and the oracle's literal product is
-    reproduced."""
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_singular_non_unitary_and_off_diagonal_pivots(dt):
+    """Non-unitary matrices are factored like unitary ones while their pending
+    factors stay in bounds, and applied whole otherwise; a singular matrix
+    (a projector) cannot be factored; near-exchanges put the larger
+    first-row entry off the diagonal (an exchange runs first).  The oracle's
+    literal products are reproduced."""
     n = 12
-    _say("non-unitary matrices")
+    _say(f"non-unitary, singular and off-diagonal pivots {dt}")
     rng = np.random.default_rng(3)
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
     recs = []
-    for layer in range(6):
+    for layer in range(8):
         for q in range(n):
             m = haar_u2(rng)
-            if (q + layer) % 5 == 0:
+            sel = (q + layer) % 6
+            if sel == 0:
                 m = 0.9 * m  # not unitary
+            elif sel == 1:
+                m = X @ np.diag([1.0, np.exp(0.3j * q)]) + 1e-3 * haar_u2(rng)  # near an exchange
+            elif sel == 2 and layer % 4 == 1:
+                m = np.array([[1, 0], [0, 0]], dtype=complex)  # projector: singular
+            elif sel == 3:
+                m = np.array([[1.0, 0.2], [0.1, 7.0]], dtype=complex)  # far from unitary
             recs.append((KIND_U, q, -1, m))
-        for q in range(0, n - 1, 2):
+        for q in range(layer % 2, n - 1, 2):
             recs.append((KIND_CU, q, q + 1, haar_u2(rng)))
+        recs.append((KIND_CX, (layer * 5) % n, (layer * 5 + 3) % n, None))
     g = make_gates(recs)
-    assert np.abs(_run(g, n, "c128", form="pass", k_tile=9, max_swaps=4) - O.run(g, n)).max() <= 1e-12
+    ref = O.run(g, n)
+    scale = max(1.0, np.abs(ref).max())
+    got = _run(g, n, dt, form="pass", k_tile=9, max_swaps=4)
+    assert np.abs(got - ref).max() <= TOL[dt] * scale
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_long_program_scalar_stays_bounded(dt):
+    """400 layers on 12 qubits: without the bound the product of the pivots
+    would leave complex64's range; a gate applied whole takes the scalar
+    whenever its magnitude would leave [2^-8, 2^8]."""
+    n = 12
+    _say(f"long program {dt}")
+    g = layered_circuit(n, 400, seed=91)
+    opts = dict(form="pass", k_tile=10, max_swaps=4, pinned=3, perm_exec="relabel")
+    P = Q.Program(g, n, dt, **opts)
+    c = P.op_counts()
+    P.close()
+    n_u = int(sum(1 for k in g["kind"] if k == KIND_U))
+    assert c["shear"] > 0.9 * n_u and c["u"] > n
+    ref = O.run(g, n)
+    got = _run(g, n, dt, **opts)
+    assert np.abs(got - ref).max() <= TOL[dt]
+    if dt == "c64":
+        fid = abs(np.vdot(ref, got)) ** 2 / np.vdot(got, got).real
+        assert 1 - fid <= 1e-6
