@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many GiB 3 times (a plain copy kernel of "
                          "known size, used to scale hardware byte counters)")
+    ap.add_argument("--traffic-from", default=None, metavar="FETCH_DIR,WRITE_DIR",
+                    help="write --traffic-json from two rocprofv3 --pmc runs of this script with --copy-calib "
+                         "(FETCH_SIZE, then WRITE_SIZE; CSV output directories) and exit")
     ap.add_argument("--forms", default="precision,batch,serve",
                     help="forms timed after the headline and reported as sub-objects of its line (comma-separated "
                          "subset of precision, batch, serve; empty: none)")
@@ -101,6 +104,42 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_2010_09746_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def traffic_from_counters(a):
+    """HBM bytes per tile-pass launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch, two rocprofv3 --pmc runs of this script with --copy-calib G),
+    each scaled by what the same counter reads for the plain copies of G GiB
+    (the largest copy dispatches of the run); written to --traffic-json with
+    the hash of the kernel sources they describe."""
+    import csv
+    import glob
+
+    dirs = a.traffic_from.split(",")
+    out = {"kernel": None, "kernel_source_sha1": kernel_source_hash(), "calibration": {}, "counters_KiB": {}}
+    scales = {}
+    for ctr, d in zip(("FETCH_SIZE", "WRITE_SIZE"), dirs):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == ctr]
+        tile = [float(r["Counter_Value"]) for r in rows if "k_tile<double, 8, 4" in r["Kernel_Name"]]
+        copy = sorted(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])[-3:]
+        if not tile or len(copy) < 3:
+            raise SystemExit(f"{d}: no tile-pass or copy dispatches for {ctr}")
+        out["kernel"] = next(r["Kernel_Name"] for r in rows if "k_tile<double, 8, 4" in r["Kernel_Name"])
+        copy_kib = sum(copy) / len(copy)
+        scales[ctr] = (a.copy_calib << 30) / (copy_kib * 1024.0)
+        out["calibration"][ctr] = {"copy_bytes_per_dispatch": a.copy_calib << 30, "copy_KiB": copy_kib,
+                                   "scale": scales[ctr]}
+        out["counters_KiB"][ctr] = sum(tile) / len(tile)
+    per_launch = sum(out["counters_KiB"][c] * 1024.0 * scales[c] for c in scales)
+    out["bytes_per_launch"] = {f"n{a.n}_{a.dtype}_k{a.k}_r{a.r}_{a.perm_exec}": per_launch}
+    out["commands"] = [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o run -- python3 bench.py --steps 1 "
+                       f"--warmup 0 --plain-steps 0 --cpu-seconds 0 --forms= --copy-calib {a.copy_calib}"
+                       for c in ("FETCH_SIZE", "WRITE_SIZE")]
+    with open(a.traffic_json, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 def cpu_model():
@@ -457,6 +496,8 @@ def costmodel_form(a):
 
 def main():
     a = parse()
+    if a.traffic_from:
+        return traffic_from_counters(a)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)

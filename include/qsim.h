@@ -101,16 +101,17 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *   flags      QS_OPT_FULL_MATRICES: every one-qubit gate of a tile pass is
  *              applied as its whole 2x2 matrix.  Without it (0, the
  *              default) an uncontrolled gate M on qubit q (with q's pending
- *              diagonal absorbed) is factored as
- *              M = M00 diag(1, z) [[1, 0], [q, 1]] [[1, p], [0, 1]]
- *              (or the same for M X, after an exchange that relabels
- *              register slots, when |M01| > |M00|): two in-place shears,
- *              8 real multiply-adds per amplitude pair instead of 16.
- *              diag(1, z) is kept pending on q and absorbed by q's next
- *              one-qubit gate, or applied before an operation that acts on
- *              q non-diagonally; M00 goes into one scalar that the next
- *              gate applied whole takes, and the last gate of each qubit
- *              is applied whole.  Same result up to rounding.
+ *              factor absorbed) is factored as F [[1, 0], [q, 1]] [[1, p],
+ *              [0, 1]] (or the same for M X, after an exchange that
+ *              relabels register slots): two in-place shears, 8 real
+ *              multiply-adds per amplitude pair instead of 16.  The left
+ *              factor F is kept pending on q and absorbed by q's next
+ *              one-qubit gate: F = a I + b X when q's operations up to that
+ *              gate are all CNOT targets (it commutes with them), else
+ *              M00 diag(1, z), applied before an operation that acts on q
+ *              non-diagonally, with M00 in one scalar that the next gate
+ *              applied whole takes.  The last gate of each qubit is applied
+ *              whole.  Same result up to rounding.
  */
 enum { QS_OPT_FULL_MATRICES = 1 };
 typedef struct {
@@ -201,6 +202,7 @@ qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
  *                      of the fractions of amplitudes they move
  *   QS_OPC_SHEAR       one-qubit updates as two shears (see flags)
  *   QS_OPC_PHASE       pending diagonals applied on their own (see flags)
+ *   QS_OPC_LSWAP       exchanges of a register bit with a lane bit in registers
  * Writes min(cap, QS_OPC_COUNT) entries. */
 enum {
     QS_OPC_TILE_PASS = 0,
@@ -220,7 +222,8 @@ enum {
     QS_OPC_MOVE_FRACTION = 14,
     QS_OPC_SHEAR = 15,     /* one-qubit update as two shears */
     QS_OPC_PHASE = 16,     /* pending diagonal applied on its own */
-    QS_OPC_COUNT = 17
+    QS_OPC_LSWAP = 17,     /* register slot bit <-> lane bit exchange (no LDS) */
+    QS_OPC_COUNT = 18
 };
 qs_status qs_program_op_counts(const qs_program *p, double *out, int cap);
 

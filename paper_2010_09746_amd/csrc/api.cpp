@@ -689,6 +689,14 @@ qs_status qs_program_op_counts(const qs_program *p, double *out, int cap)
                         c[QS_OPC_REMAP] += 1;
                         continue;
                     }
+                    if (o.kind == OP_SHEAR2) {
+                        c[QS_OPC_SHEAR] += 2;
+                        continue;
+                    }
+                    if (o.kind == OP_LSWAP) {
+                        c[QS_OPC_LSWAP] += 1;
+                        continue;
+                    }
                     const double w = std::ldexp(1.0, -__builtin_popcountll(o.hmask));
                     const bool ctrl = (o.rmask | o.lmask) != 0;
                     c[QS_OPC_DISPATCH] += 1.0 - w;

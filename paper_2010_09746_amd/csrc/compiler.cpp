@@ -364,6 +364,7 @@ struct LGate {
     uint64_t hmask, hbit;
     double m[8];
     int q[2], nq;    // logical qubits (for in-segment dependencies)
+    int qtb[2];      // tile bit of each logical qubit, -1 outside the tile
     int src;         // index into the source gate array
 };
 
@@ -375,6 +376,8 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
     L.nq = gi.nq;
     L.q[0] = gi.q0;
     L.q[1] = gi.q1;
+    for (int k = 0; k < gi.nq; ++k)
+        L.qtb[k] = tile_bit_of_pos[sigma_phys[L.q[k]]];
     std::memcpy(L.m, g.u, sizeof L.m);
     auto add_ctrl = [&](int q) {
         int p = sigma_phys[q];
@@ -435,7 +438,7 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 }
 
 // ---------------------------------------------------------------------------
-// Pending one-qubit phases (lowering only; the pass is unchanged).
+// Pending one-qubit factors (lowering only; the pass is unchanged).
 //
 // Every invertible 2x2 matrix M with M00 != 0 factors as
 //   M = M00 diag(1, z) L(q) U(p),  U(p) = [[1, p], [0, 1]], L(q) = [[1, 0], [q, 1]],
@@ -446,43 +449,88 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 // temporary.  When |M01| > |M00| the same is done for M X = [[M01, M00],
 // [M11, M10]] (det M X = -det M) and an exchange X on the qubit runs first
 // (flagged on the op: an uncontrolled exchange on a register slot is a
-// relabelling of slots and moves no data).  Pivoting on the larger entry of the first row keeps
-// |p| <= 1.
+// relabelling of slots and moves no data).  Pivoting on the larger entry of
+// the first row keeps |p| <= 1.
+//
+// M also factors as M = (a I + b X) L(q) U(p) (or with an exchange first):
+// N = (a I + b X)^-1 M must have N00 = 1 and det N = 1, which fixes a and b
+// up to the two roots of a quadratic (solved below).  The left factor
+// commutes with every operation that acts on the qubit as a matrix in
+// span{I, X} (the target of a CNOT), where diag(1, z) does not.
 //
 // The lowering applies the shears of each uncontrolled one-qubit gate in a
-// tile pass and keeps diag(1, z) pending on the gate's qubit q, and the factor
-// M00 in one scalar for the whole state: the stored state equals the true
-// state with the pending diagonals and the scalar divided out.  A pending
-// diagonal commutes with every operation that acts diagonally on q (CZ, a
-// control on q), so it stays pending through them.  The next one-qubit gate
-// on q absorbs it into its own matrix (host arithmetic, no device work); an
-// operation that acts on q non-diagonally otherwise (the target of a CNOT or
-// of a controlled gate) needs it applied first, as a multiplication of the
-// amplitudes whose bit q is 1 (OP_PHASE; with the shears 12 multiply-adds,
-// still fewer than a general 2x2).  The last one-qubit gate of each qubit is
-// applied whole with its qubit's pending diagonal absorbed, and a gate
-// applied whole also takes the scalar (it touches every amplitude), so the
-// state is exact (up to rounding) when the program ends.  The stored
-// amplitudes stay within a bounded factor of the true ones: a gate is applied
-// whole instead when its new pending |z| would leave [1/4, 4], the scalar's
-// magnitude [2^-8, 2^8], or |q| exceed 16, so that complex64 states keep at
-// least 2^-(2n+8) of their magnitude range.
+// tile pass and keeps the left factor pending on the gate's qubit: diag(1, z)
+// (with M00 moved into one scalar for the whole state) when the operations on
+// the qubit up to its next one-qubit gate act on it diagonally (CZ, a
+// control), a I + b X when they are all CNOT targets.  The stored state equals
+// the true state with the pending factors and the scalar divided out.  The
+// next one-qubit gate on the qubit absorbs its pending factor into its own
+// matrix (host arithmetic, no device work).  An operation that does not
+// commute with the pending factor needs it applied first: diag(1, z) before a
+// non-diagonal target, as a multiplication of the amplitudes whose bit is 1
+// (OP_PHASE), and a I + b X before a diagonal action or a general target, as a
+// whole 2x2.  The latter cannot be needed before a diagonal action: such an
+// operation between the gate and the next one-qubit gate on the qubit would
+// have chosen the diagonal form, and any other is ordered before the gate or
+// after that next gate by the commutation DAG (a diagonal action does not
+// commute with a non-diagonal one-qubit gate).  The last one-qubit gate of each
+// qubit is applied whole with its pending factor absorbed, and a gate applied
+// whole also takes the scalar (it touches every amplitude), so the state is
+// exact (up to rounding) when the program ends.  The stored amplitudes stay
+// within a bounded factor of the true ones: a gate is applied whole instead
+// when the new pending factor's condition number would exceed 4 for
+// diag(1, z) (|z| outside [1/4, 4]) or 8 for a I + b X (|a + b| / |a - b| or its
+// inverse; for unitary M the best root reaches 5.8), its determinant leave
+// [1/16, 16], the scalar's magnitude [2^-8, 2^8], or |p|, |q| exceed 16,
+// so that complex64 states keep at least 2^-(2n+8) of their magnitude range.
 struct PhaseFrame {
     using cd = std::complex<double>;
     static constexpr double Z_LO = 0.25, Z_HI = 4.0, S_LO = 1.0 / 256.0, S_HI = 256.0, Q_MAX = 16.0;
+    static constexpr double DET_LO = 1.0 / 16.0, DET_HI = 16.0, K_X = 8.0;
+    enum : int8_t { P_NONE = 0, P_DIAG = 1, P_XT = 2 };
+    enum Action { A_DIAG, A_X, A_GEN };
     bool on = false;
-    std::vector<cd> z;            // pending diag(1, z[q]) per logical qubit
-    std::vector<int64_t> u_left;  // non-diagonal one-qubit gates of q not yet lowered
-    cd scalar{1.0, 0.0};          // accumulated product of the pivots
+    // pending factor per logical qubit: P_DIAG diag(1, z[q]); P_XT a[q] I + b[q] X
+    std::vector<int8_t> type;
+    std::vector<cd> z, a, b;
+    std::vector<int64_t> u_left;   // non-diagonal one-qubit gates of q not yet lowered
+    std::vector<char> prefer_x;    // per gate: its pending factor should commute with X
+    cd scalar{1.0, 0.0};           // accumulated product of the pivots
+
+    static bool absorbing(const qs_gate &g, const GateInfo &gi) { return g.kind == QS_GATE_U && gi.act0 != ACT_Z; }
+    // how gate gi acts on qubit q (it acts on q)
+    static Action action(const GateInfo &gi, int q)
+    {
+        const int act = q == gi.q0 ? gi.act0 : gi.act1;
+        return act == ACT_Z ? A_DIAG : act == ACT_X && gi.nq == 2 ? A_X : A_GEN;
+    }
 
     void init(const qs_gate *g, const std::vector<GateInfo> &gi, int64_t ng, int n)
     {
+        type.assign(n, P_NONE);
         z.assign(n, cd(1.0, 0.0));
+        a.assign(n, cd(1.0, 0.0));
+        b.assign(n, cd(0.0, 0.0));
         u_left.assign(n, 0);
         scalar = cd(1.0, 0.0);
-        for (int64_t v = 0; v < ng; ++v)
-            if (g[v].kind == QS_GATE_U && gi[v].act0 != ACT_Z)
+        prefer_x.assign(ng, 0);
+        // for each qubit, walking backwards: do the operations on it up to its
+        // next one-qubit gate all act on it as CNOT targets (and is there one)?
+        std::vector<int> state(n, 0);  // 0 none yet, 1 all X so far, 2 mixed
+        for (int64_t v = ng - 1; v >= 0; --v) {
+            const int qs[2] = {gi[v].q0, gi[v].q1};
+            for (int k = 0; k < gi[v].nq; ++k) {
+                const int q = qs[k];
+                if (absorbing(g[v], gi[v])) {
+                    prefer_x[v] = state[q] == 1;
+                    state[q] = 0;
+                } else {
+                    state[q] = action(gi[v], q) == A_X && state[q] != 2 ? 1 : 2;
+                }
+            }
+            if (absorbing(g[v], gi[v]))
                 ++u_left[g[v].q0];
+        }
     }
     static cd at(const double *m, int i) { return cd(m[2 * i], m[2 * i + 1]); }
     static void put(double *m, int i, cd c)
@@ -490,30 +538,115 @@ struct PhaseFrame {
         m[2 * i] = c.real();
         m[2 * i + 1] = c.imag();
     }
-    // Lower the uncontrolled one-qubit gate u on logical qubit q: writes the
-    // op's kind and matrix fields (OP_SHEAR: m[0..1] = p, m[2..3] = q; OP_U:
-    // the whole matrix) and *flip, true when an uncontrolled exchange on q
-    // must run just before the op; updates the pending diagonal of q.
-    void one_qubit(int q, const double *u, int32_t *kind, double *m, bool *flip)
+    void clear(int q)
     {
-        const cd M[4] = {at(u, 0), at(u, 1) * z[q], at(u, 2), at(u, 3) * z[q]};
+        type[q] = P_NONE;
+        z[q] = a[q] = cd(1.0, 0.0);
+        b[q] = cd(0.0, 0.0);
+    }
+    // M = u P: the gate's matrix with qubit q's pending factor absorbed
+    void absorb(int q, const double *u, cd M[4]) const
+    {
+        const cd u00 = at(u, 0), u01 = at(u, 1), u10 = at(u, 2), u11 = at(u, 3);
+        if (type[q] == P_XT) {
+            M[0] = u00 * a[q] + u01 * b[q];
+            M[1] = u00 * b[q] + u01 * a[q];
+            M[2] = u10 * a[q] + u11 * b[q];
+            M[3] = u10 * b[q] + u11 * a[q];
+        } else {
+            M[0] = u00;
+            M[1] = u01 * z[q];
+            M[2] = u10;
+            M[3] = u11 * z[q];
+        }
+    }
+    // M = (a I + b X) L(q) U(p) X^x with the best-conditioned left factor;
+    // false when none is within the bounds
+    static bool factor_x(const cd M[4], cd *pa, cd *pb, cd *pp, cd *pq, bool *px)
+    {
+        double best = 0.0;
+        bool found = false;
+        for (int x = 0; x < 2; ++x) {
+            // columns exchanged with the exchange first
+            const cd m00 = x ? M[1] : M[0], m01 = x ? M[0] : M[1], m10 = x ? M[3] : M[2], m11 = x ? M[2] : M[3];
+            const cd D = m00 * m11 - m01 * m10;
+            // a m00 - b m10 = D and a^2 - b^2 = D:
+            // b^2 (m10^2 - m00^2) + 2 D m10 b + D^2 - D m00^2 = 0
+            const cd A = m10 * m10 - m00 * m00, B = 2.0 * D * m10, C = D * D - D * m00 * m00;
+            if (std::abs(m00) == 0.0 || std::abs(D) == 0.0)
+                continue;
+            const cd disc = std::sqrt(B * B - 4.0 * A * C);
+            for (int r = 0; r < 2; ++r) {
+                const cd den = r ? -B + disc : -B - disc;  // b = 2C / den (stable for both roots)
+                if (std::abs(den) == 0.0)
+                    continue;
+                const cd bb = 2.0 * C / den, aa = (D + bb * m10) / m00;
+                const cd det = aa * aa - bb * bb;
+                if (std::abs(det) == 0.0)
+                    continue;
+                // N = (a I - b X) M / det: N01 = p, N10 = q
+                const cd p = (aa * m01 - bb * m11) / det, q = (aa * m10 - bb * m00) / det;
+                const double e1 = std::abs(aa + bb), e2 = std::abs(aa - bb);
+                if (e1 == 0.0 || e2 == 0.0)
+                    continue;
+                const double kappa = std::max(e1 / e2, e2 / e1), ad = std::abs(det);
+                if (kappa > K_X || ad < DET_LO || ad > DET_HI || std::abs(p) > Q_MAX || std::abs(q) > Q_MAX)
+                    continue;
+                if (!found || kappa < best) {
+                    found = true;
+                    best = kappa;
+                    *pa = aa;
+                    *pb = bb;
+                    *pp = p;
+                    *pq = q;
+                    *px = x != 0;
+                }
+            }
+        }
+        return found;
+    }
+    // Lower the uncontrolled one-qubit gate v (matrix u) on logical qubit q:
+    // writes the op's kind and matrix fields (OP_SHEAR: m[0..1] = p, m[2..3] =
+    // q; OP_U: the whole matrix) and *flip, true when an uncontrolled exchange
+    // on q must run just before the op; updates the pending factor of q.
+    // v < 0: the gate is applied whole.
+    void one_qubit(int64_t v, int q, const double *u, int32_t *kind, double *m, bool *flip)
+    {
+        cd M[4];
+        absorb(q, u, M);
         *flip = false;
         std::memset(m, 0, 8 * sizeof(double));
-        if (--u_left[q] > 0) {
+        if (--u_left[q] > 0 && v >= 0) {
+            cd pa, pb, pp, pq;
+            bool x;
+            if (prefer_x[v] && factor_x(M, &pa, &pb, &pp, &pq, &x)) {
+                *kind = OP_SHEAR;
+                *flip = x;
+                put(m, 0, pp);
+                put(m, 1, pq);
+                type[q] = P_XT;
+                a[q] = pa;
+                b[q] = pb;
+                z[q] = cd(1.0, 0.0);
+                return;
+            }
             const cd det = M[0] * M[3] - M[1] * M[2];
-            const bool x = std::abs(M[1]) > std::abs(M[0]);
-            const cd piv = x ? M[1] : M[0];
+            const bool xx = std::abs(M[1]) > std::abs(M[0]);
+            const cd piv = xx ? M[1] : M[0];
             // with the exchange: M X = [[M01, M00], [M11, M10]], det M X = -det M
-            const cd p = (x ? M[0] : M[1]) / piv, qq = x ? -M[3] * piv / det : M[2] * piv / det;
-            const cd zn = x ? -det / (piv * piv) : det / (piv * piv), sn = scalar * piv;
+            const cd p = (xx ? M[0] : M[1]) / piv, qq = xx ? -M[3] * piv / det : M[2] * piv / det;
+            const cd zn = xx ? -det / (piv * piv) : det / (piv * piv), sn = scalar * piv;
             const double az = std::abs(zn), as = std::abs(sn);
             if (std::abs(det) > 0.0 && az >= Z_LO && az <= Z_HI && as >= S_LO && as <= S_HI &&
                 std::abs(qq) <= Q_MAX) {
                 *kind = OP_SHEAR;
-                *flip = x;
+                *flip = xx;
                 put(m, 0, p);
                 put(m, 1, qq);
+                type[q] = P_DIAG;
                 z[q] = zn;
+                a[q] = cd(1.0, 0.0);
+                b[q] = cd(0.0, 0.0);
                 scalar = sn;
                 return;
             }
@@ -522,19 +655,30 @@ struct PhaseFrame {
         for (int i = 0; i < 4; ++i)
             put(m, i, M[i] * scalar);
         scalar = cd(1.0, 0.0);
-        z[q] = cd(1.0, 0.0);
+        clear(q);
     }
-    // Before an operation that acts on q non-diagonally other than a
-    // one-qubit gate: returns true, with the pending factor in *out, when the
-    // caller must apply diag(1, *out) on q first.
-    bool settle(int q, cd *out)
+    // Before gate gi acts on q with the given action: what of q's pending
+    // factor must be applied first, as a 2x2 matrix in out[8] (the record
+    // layout of qs_gate.u).  Returns 0 (nothing), 1 (diag(1, z): a phase on
+    // the amplitudes whose bit is 1, out[6..7] = z) or 2 (a whole 2x2).
+    int settle(int q, Action act, double *out)
     {
-        const cd ph = z[q];
-        z[q] = cd(1.0, 0.0);
-        if (ph == cd(1.0, 0.0))
-            return false;
-        *out = ph;
-        return true;
+        std::memset(out, 0, 8 * sizeof(double));
+        if (type[q] == P_DIAG && act != A_DIAG) {
+            put(out, 0, cd(1.0, 0.0));
+            put(out, 3, z[q]);
+            clear(q);
+            return 1;
+        }
+        if (type[q] == P_XT && act != A_X) {
+            put(out, 0, a[q]);
+            put(out, 1, b[q]);
+            put(out, 2, b[q]);
+            put(out, 3, a[q]);
+            clear(q);
+            return 2;
+        }
+        return 0;
     }
 };
 
@@ -559,6 +703,7 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
         }
     std::vector<char> emitted(cnt, 0);
     int left = cnt, remaps = 0;
+    const size_t seg_begin = ops.size();
     const int R = log_r;
     int regs[8];
     bool have = false;
@@ -618,26 +763,50 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
                 op.hbit = lg[v].hbit;
                 std::memcpy(op.m, lg[v].m, sizeof op.m);
                 if (pf.on) {
-                    const qs_gate &src = g[lg[v].src];
-                    if (src.kind == QS_GATE_U && op.kind == OP_U) {
+                    const int64_t sv = lg[v].src;
+                    const qs_gate &src = g[sv];
+                    if (PhaseFrame::absorbing(src, gi[sv])) {
                         bool flip = false;
-                        pf.one_qubit(src.q0, src.u, &op.kind, op.m, &flip);
+                        pf.one_qubit(sv, src.q0, src.u, &op.kind, op.m, &flip);
                         op.tlane = flip ? 1u : 0u;
-                    } else if (needs_reg(v)) {
-                        // X-type target of a CNOT, or the target of a
-                        // controlled 2x2: the pending diagonal goes first
-                        std::complex<double> ph;
-                        if (pf.settle(src.q1, &ph)) {
+                    } else {
+                        // pending factors that do not commute with this
+                        // operation go first (on a register slot: the
+                        // qubit is the operation's target, see PhaseFrame)
+                        for (int a = 0; a < lg[v].nq; ++a) {
+                            double sm[8];
+                            const int q = lg[v].q[a];
+                            const int how = pf.settle(q, PhaseFrame::action(gi[sv], q), sm);
+                            if (how == 0)
+                                continue;
+                            const int s = lg[v].qtb[a] >= 0 ? in_regs(lg[v].qtb[a]) : -1;
+                            if (s < 0)
+                                fail(QS_ERR_STATE, "internal: pending factor on a qubit outside the register slots");
                             TileOp po{};
-                            po.kind = OP_PHASE;
-                            po.slot = slot;
-                            po.m[0] = ph.real();
-                            po.m[1] = ph.imag();
+                            po.slot = s;
+                            if (how == 1) {
+                                po.kind = OP_PHASE;
+                                po.m[0] = sm[6];
+                                po.m[1] = sm[7];
+                            } else {
+                                po.kind = OP_U;
+                                std::memcpy(po.m, sm, sizeof po.m);
+                            }
                             ops.push_back(po);
                         }
                     }
                 }
-                ops.push_back(op);
+                // a shear right after a shear on another slot of this pass
+                // shares its record (one fetch and dispatch for two gates)
+                if (op.kind == OP_SHEAR && ops.size() > seg_begin && ops.back().kind == OP_SHEAR &&
+                    ops.back().slot != op.slot) {
+                    TileOp &prev = ops.back();
+                    prev.kind = OP_SHEAR2;
+                    prev.aux = (uint32_t)op.slot | (op.tlane ? 256u : 0u);
+                    std::memcpy(prev.m + 4, op.m, 4 * sizeof(double));
+                } else {
+                    ops.push_back(op);
+                }
                 emitted[v] = 1;
                 --left;
                 progress = true;
@@ -713,6 +882,10 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
             packed |= (uint32_t)want[s] << (4 * s);
         }
         op.rmask = packed;
+        uint32_t words[16] = {};
+        for (int s = 0; s < R; ++s)
+            words[s] = lds_swizzle(1u << want[s], k);
+        std::memcpy(op.m, words, sizeof op.m);
         // thread-id bits take the other tile bits in ascending order
         uint64_t lanes = 0;
         for (int b = 0, i = 0; b < k; ++b) {
@@ -730,32 +903,110 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
     return remaps;
 }
 
-// A tile is loaded straight into the layout of its first OP_REMAP (and stored
-// straight from its last one) when the thread bits of that layout include the
-// lowest tile bits, so that each load or store instruction still moves runs
-// of DIRECT_RUN_BYTES contiguous bytes.  Otherwise it is loaded (stored) in
-// tile-local index order j * NT + tid and goes through LDS.
-void set_direct_io(Launch &L, const std::vector<TileOp> &ops, qs_dtype dt)
+// Tile bits that must be thread bits for each load or store instruction to
+// move runs of DIRECT_RUN_BYTES contiguous bytes, and whether the tile's
+// lowest positions are the lowest physical positions (else no run is that
+// long whatever the layout).
+int direct_low_bits(qs_dtype dt)
 {
     const int esize = dt == QS_C64 ? 8 : 16;
-    int low = 0;  // tile bits that must be thread bits
+    int low = 0;
     while ((esize << low) < DIRECT_RUN_BYTES)
         ++low;
+    return low;
+}
+bool low_positions_contiguous(const Launch &L, int low)
+{
     bool contiguous = true;
     for (int b = 0; b < low && b < L.k; ++b)
         contiguous &= L.pos[b] == b;
-    auto lanes_cover_low = [&](uint32_t regs) {
+    return contiguous;
+}
+
+// The layout in force after the launch's last operation: register tile bits
+// per slot and tile bit per thread bit (the last OP_REMAP and the OP_LSWAPs
+// after it); false when the launch has no OP_REMAP.
+bool final_layout(const Launch &L, const std::vector<TileOp> &ops, int *regs, int *lanes)
+{
+    const TileOp *o = ops.data() + L.op_begin;
+    int last = -1;
+    for (int i = L.op_count - 1; i >= 0 && last < 0; --i)
+        if (o[i].kind == OP_REMAP)
+            last = i;
+    if (last < 0)
+        return false;
+    for (int s = 0; s < L.log_r; ++s)
+        regs[s] = (int)((o[last].rmask >> (4 * s)) & 15u);
+    for (int i = 0; i < L.log_nt; ++i)
+        lanes[i] = (int)((o[last].hbit >> (4 * i)) & 15u);
+    for (int i = last + 1; i < L.op_count; ++i)
+        if (o[i].kind == OP_LSWAP)
+            std::swap(regs[o[i].slot], lanes[o[i].tlane]);
+    return true;
+}
+
+// When the last layout of a tile pass keeps one or two of the lowest tile
+// bits in register slots, the store would go through an LDS re-layout to the
+// plain layout.  Exchanging those slot bits with lane bits 4 and 5 of the
+// wavefront (OP_LSWAP: cross-lane swaps in registers, no LDS and no barrier)
+// puts them on thread bits instead, so the tile is stored straight from
+// registers: the eight (complex128) or sixteen (complex64) amplitudes of a
+// 128-byte line then sit in lanes of one store instruction.
+void append_store_lane_swaps(Launch &L, std::vector<TileOp> &ops, qs_dtype dt)
+{
+    const int low = direct_low_bits(dt);
+    if (L.op_count == 0 || !low_positions_contiguous(L, low) || L.log_nt < 6)
+        return;
+    int regs[8], lanes[16];
+    if (!final_layout(L, ops, regs, lanes))
+        return;
+    std::vector<int> slots;
+    for (int s = 0; s < L.log_r; ++s)
+        if (regs[s] < low)
+            slots.push_back(s);
+    std::vector<int> free_lanes;
+    for (int b : {5, 4})
+        if (lanes[b] >= low)
+            free_lanes.push_back(b);
+    if (slots.empty() || slots.size() > free_lanes.size())
+        return;
+    for (size_t i = 0; i < slots.size(); ++i) {
+        const int s = slots[i], b = free_lanes[i];
+        TileOp op{};
+        op.kind = OP_LSWAP;
+        op.slot = s;
+        op.tlane = (uint32_t)b;
+        op.lmask = 1u << lanes[b];
+        op.rmask = 1u << regs[s];
+        const uint32_t w = lds_swizzle(1u << lanes[b], L.k);
+        std::memcpy(op.m, &w, sizeof w);
+        ops.push_back(op);
+        ++L.op_count;
+        std::swap(regs[s], lanes[b]);
+    }
+}
+
+// A tile is loaded straight into the layout of its first OP_REMAP (and stored
+// straight from its final layout) when the thread bits of that layout include
+// the lowest tile bits, so that each load or store instruction still moves
+// runs of DIRECT_RUN_BYTES contiguous bytes.  Otherwise it is loaded (stored)
+// in tile-local index order j * NT + tid and goes through LDS.
+void set_direct_io(Launch &L, const std::vector<TileOp> &ops, qs_dtype dt)
+{
+    const int low = direct_low_bits(dt);
+    const bool contiguous = low_positions_contiguous(L, low);
+    auto covers_low = [&](const int *regs) {
         for (int s = 0; s < L.log_r; ++s)
-            if ((int)((regs >> (4 * s)) & 15u) < low)
+            if (regs[s] < low)
                 return false;
         return contiguous;
     };
-    // positions of a layout given by packed register tile bits and lane map
-    auto layout = [&](uint32_t regs, uint64_t lanes, uint8_t *lane, uint8_t *reg) {
+    // positions of a layout given by register tile bits and lane tile bits
+    auto layout = [&](const int *regs, const int *lanes, uint8_t *lane, uint8_t *reg) {
         for (int i = 0; i < L.log_nt; ++i)
-            lane[i] = (uint8_t)L.pos[(lanes >> (4 * i)) & 15u];
+            lane[i] = (uint8_t)L.pos[lanes[i]];
         for (int s = 0; s < L.log_r; ++s)
-            reg[s] = (uint8_t)L.pos[(regs >> (4 * s)) & 15u];
+            reg[s] = (uint8_t)L.pos[regs[s]];
     };
     auto plain = [&](uint8_t *lane, uint8_t *reg) {
         for (int i = 0; i < L.log_nt; ++i)
@@ -769,18 +1020,19 @@ void set_direct_io(Launch &L, const std::vector<TileOp> &ops, qs_dtype dt)
     const TileOp *o = ops.data() + L.op_begin;
     if (L.op_count == 0 || o[0].kind != OP_REMAP)
         return;
-    if (lanes_cover_low(o[0].rmask)) {
+    int regs[8], lanes[16];
+    for (int s = 0; s < L.log_r; ++s)
+        regs[s] = (int)((o[0].rmask >> (4 * s)) & 15u);
+    for (int i = 0; i < L.log_nt; ++i)
+        lanes[i] = (int)((o[0].hbit >> (4 * i)) & 15u);
+    if (covers_low(regs)) {
         L.io |= 1u;
-        layout(o[0].rmask, o[0].hbit, L.ld_lane, L.ld_reg);
+        layout(regs, lanes, L.ld_lane, L.ld_reg);
     }
-    for (int i = L.op_count - 1; i >= 0; --i)
-        if (o[i].kind == OP_REMAP) {
-            if (lanes_cover_low(o[i].rmask)) {
-                L.io |= 2u;
-                layout(o[i].rmask, o[i].hbit, L.st_lane, L.st_reg);
-            }
-            break;
-        }
+    if (final_layout(L, ops, regs, lanes) && covers_low(regs)) {
+        L.io |= 2u;
+        layout(regs, lanes, L.st_lane, L.st_reg);
+    }
 }
 
 }  // namespace
@@ -864,28 +1116,24 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         L.gate.q0 = sphys[g[v].q0];
         L.gate.q1 = g[v].kind == QS_GATE_U ? -1 : sphys[g[v].q1];
         if (pf.on) {
-            if (g[v].kind == QS_GATE_U && gi[v].act0 != ACT_Z) {
-                // one launch of the whole matrix with the pending phase absorbed
+            if (PhaseFrame::absorbing(g[v], gi[v])) {
+                // one launch of the whole matrix with the pending factor absorbed
                 int32_t kind = OP_U;
-                double m[8];
                 bool flip = false;
-                const int64_t left = pf.u_left[g[v].q0];
-                pf.u_left[g[v].q0] = 1;  // forces the whole-matrix form
-                pf.one_qubit(g[v].q0, g[v].u, &kind, m, &flip);
-                pf.u_left[g[v].q0] = left - 1;
-                std::memcpy(L.gate.u, m, sizeof m);
-            } else if ((g[v].kind == QS_GATE_CX || g[v].kind == QS_GATE_CU) && gi[v].act1 != ACT_Z) {
-                std::complex<double> ph;
-                if (pf.settle(g[v].q1, &ph)) {
+                pf.one_qubit(-1, g[v].q0, g[v].u, &kind, L.gate.u, &flip);
+            } else {
+                // pending factors that do not commute with the gate go first,
+                // each as a one-qubit launch of its own
+                const int qs[2] = {g[v].q0, g[v].q1};
+                for (int a = 0; a < gi[v].nq; ++a) {
                     Launch D;
                     D.type = L_PLAIN;
                     D.gate = qs_gate{};
+                    if (pf.settle(qs[a], PhaseFrame::action(gi[v], qs[a]), D.gate.u) == 0)
+                        continue;
                     D.gate.kind = QS_GATE_U;
-                    D.gate.q0 = sphys[g[v].q1];
+                    D.gate.q0 = sphys[qs[a]];
                     D.gate.q1 = -1;
-                    D.gate.u[0] = 1.0;
-                    D.gate.u[6] = ph.real();
-                    D.gate.u[7] = ph.imag();
                     p.launches.push_back(D);
                     ++p.stats.n_plain;
                 }
@@ -991,6 +1239,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                     L.op_begin = (int)p.ops.size();
                     p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops, pf);
                     L.op_count = (int)p.ops.size() - L.op_begin;
+                    append_store_lane_swaps(L, p.ops, dt);
                     set_direct_io(L, p.ops, dt);
                     p.launches.push_back(L);
                     ++p.stats.n_tile_passes;

@@ -14,12 +14,21 @@ enum TileOpKind : int32_t {
     OP_X = 1,      // exchange the pair on register slot `slot`
     OP_DIAG = 2,   // multiply by d0 (m[0..1]) / d1 (m[2..3]) selected by the target bit
     OP_NEG = 3,    // negate where every control bit is 1
-    OP_REMAP = 4,  // move amplitudes through LDS to a new register layout
+    OP_REMAP = 4,  // move amplitudes through LDS to a new register layout: rmask and hbit
+                   // give its register and thread tile bits, the first words of m the
+                   // LDS slot (lds_swizzle) of each register slot bit (word s: slot bit s)
     OP_SHEAR = 5,  // on the pair (x, y) of register slot `slot`: x += p y, then y += q x, with
                    // p = (m[0], m[1]) and q = (m[2], m[3]); tlane != 0: exchange x and y
                    // first (a relabelling); no controls
     OP_PHASE = 6,  // multiply where the bit of register slot `slot` is 1 by (m[0], m[1]); no
                    // controls
+    OP_SHEAR2 = 7, // two OP_SHEARs on different register slots in one record: the first on
+                   // `slot` (m[0..3], exchange flag tlane), the second on slot aux & 255
+                   // (m[4..7], exchange flag aux >> 8)
+    OP_LSWAP = 8,  // exchange register slot bit `slot` with lane bit tlane (4 or 5) of the
+                   // wavefront, in registers: the tile bit lmask (on the lane bit) moves into
+                   // the slot, the tile bit rmask (on the slot) onto the lane bit; the first
+                   // word of m is the slot's new LDS slot (lds_swizzle of lmask)
 };
 
 // One operation of a fused tile pass (104 bytes, every field at least 32 bits
@@ -37,13 +46,26 @@ struct TileOp {
     uint32_t rmask;    // OP_REMAP: register tile bits, 4 bits each (slot s at bits 4s..4s+3)
     uint32_t lmask;
     uint32_t tlane;
-    uint32_t pad;
+    uint32_t aux;      // OP_SHEAR2: the second shear's slot and exchange flag
     uint64_t hmask;
     uint64_t hbit;     // OP_DIAG target outside the tile; OP_REMAP: the tile bit of each
                        // thread-id bit, 4 bits each (thread bit i at bits 4i..4i+3)
     double m[8];
 };
 static_assert(sizeof(TileOp) == 104, "TileOp layout");
+
+// LDS element slot of tile-local index i in a tile of 2^k amplitudes: i with
+// each higher group of 5 bits XORed into its low 5 bits.  The map is linear
+// over GF(2) and invertible, so a layout's LDS slots are XORs of a per-thread
+// and per-register-slot parts, and lanes whose indices differ only in high
+// bits land in different banks.
+constexpr uint32_t lds_swizzle(uint32_t i, int k)
+{
+    uint32_t r = i;
+    for (int s = 5; s < k; s += 5)
+        r ^= (i >> s) & 31u;
+    return r;
+}
 
 // Kernel arguments of one tile pass, passed by value.  The load and store
 // layouts give, for each thread-id bit and each register-slot bit, the

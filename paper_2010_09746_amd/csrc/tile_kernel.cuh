@@ -228,6 +228,64 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
         }
     }
 
+    // Exchange register slot bit S with lane bit 4 (L5 false) or 5 (L5 true)
+    // of the wavefront: for each register pair (a, b) of the slot, the lanes
+    // of a whose lane bit is 1 trade places with the lanes of b whose lane
+    // bit is 0 (v_permlane16_swap / v_permlane32_swap, one instruction per
+    // 32-bit word, no LDS).  With SW the slot's pattern bit is flipped: the
+    // pair is taken the other way round, and the flip stays.
+    template <bool L5> static __device__ __forceinline__ void swap_words(uint32_t &a, uint32_t &b)
+    {
+        if constexpr (L5) {
+            const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+            a = r[0];
+            b = r[1];
+        } else {
+            const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+            a = r[0];
+            b = r[1];
+        }
+    }
+    template <bool L5> static __device__ __forceinline__ void swap_real(R &a, R &b)
+    {
+        if constexpr (sizeof(R) == 8) {
+            auto x = __builtin_bit_cast(uint2, a);
+            auto y = __builtin_bit_cast(uint2, b);
+            swap_words<L5>(x.x, y.x);
+            swap_words<L5>(x.y, y.y);
+            a = __builtin_bit_cast(R, x);
+            b = __builtin_bit_cast(R, y);
+        } else {
+            uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
+            swap_words<L5>(x, y);
+            a = __builtin_bit_cast(R, x);
+            b = __builtin_bit_cast(R, y);
+        }
+    }
+    template <int S, bool L5, bool SW> static __device__ __forceinline__ void lane_swap(C (&v)[NR])
+    {
+#pragma unroll
+        for (int jj = 0; jj < NR / 2; ++jj) {
+            const int j = pair_lo<S>(jj), j1 = j | (1 << S);
+            C &a = SW ? v[j1] : v[j];
+            C &b = SW ? v[j] : v[j1];
+            swap_real<L5>(a.x, b.x);
+            swap_real<L5>(a.y, b.y);
+        }
+    }
+    template <int S = 0>
+    static __device__ __forceinline__ void dispatch_lane_swap(int slot, bool l5, uint32_t sw, C (&v)[NR])
+    {
+        if (slot == S || S == LOG_R - 1) {
+            if (l5)
+                sw ? lane_swap<S, true, true>(v) : lane_swap<S, true, false>(v);
+            else
+                sw ? lane_swap<S, false, true>(v) : lane_swap<S, false, false>(v);
+        } else if constexpr (S + 1 < LOG_R) {
+            dispatch_lane_swap<S + 1>(slot, l5, sw, v);
+        }
+    }
+
     // flip the sign bit where sg has it set (sg is 0 or the sign mask)
     static __device__ __forceinline__ R flip_sign(R x, uint32_t sg)
     {
@@ -237,8 +295,25 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
             return __builtin_bit_cast(R, __builtin_bit_cast(uint32_t, x) ^ sg);
     }
 
-    // register tile bit of slot bit s under the packed register bits regs
-    static __device__ __forceinline__ uint32_t rbit(uint32_t regs, int s) { return (regs >> (4 * s)) & 15u; }
+    // LDS byte offsets (EB times lds_swizzle of the tile bit) of the register
+    // slot bits of a layout: uniform values, shipped by the lowering with
+    // each re-layout
+    struct SlotOffs {
+        uint32_t o[LOG_R];
+    };
+    // from the record's LDS slots; opaque to the compiler, so that the
+    // addresses stay one XOR of a thread part and a scalar per slot (it
+    // otherwise moves the scaling into every address)
+    static __device__ __forceinline__ SlotOffs offs_of(const uint32_t *w)
+    {
+        SlotOffs so;
+#pragma unroll
+        for (int q = 0; q < LOG_R; ++q) {
+            so.o[q] = w[q] * EB;
+            __asm__("" : "+s"(so.o[q]));
+        }
+        return so;
+    }
 
     // Visit the slots j in Gray-code order with the XOR over the set bits s of
     // j of basis(s): consecutive slots differ in one bit, so each value costs
@@ -299,12 +374,13 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     static constexpr uint32_t LDS_BYTES = (EB << K) > 16u * NT ? (EB << K) : 16u * NT;
     // the plain layout: thread bits are tile bits 0..LOG_NT-1, slot bit s is
     // tile bit LOG_NT + s
-    static constexpr uint32_t regs_plain()
+    static __device__ __forceinline__ SlotOffs offs_plain()
     {
-        uint32_t r = 0;
+        SlotOffs so;
+#pragma unroll
         for (int s = 0; s < LOG_R; ++s)
-            r |= (uint32_t)(LOG_NT + s) << (4 * s);
-        return r;
+            so.o[s] = swz(1u << (LOG_NT + s)) * EB;
+        return so;
     }
 
     // element COMP of an amplitude in LDS: 0 real part, 1 imaginary part, 2
@@ -332,19 +408,10 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
         }
     }
 
-    // LDS slot of tile-local index i: i with each higher group of 5 bits
-    // XORed into its low 5 bits.  The map is linear over GF(2) and
-    // invertible, so a layout's addresses stay XORs of per-thread and per-slot
-    // parts; lanes whose indices differ only in high bits (thread bits placed
-    // on high tile bits by a re-layout) land in different banks instead of
-    // one.
-    static __host__ __device__ __forceinline__ constexpr uint32_t swz(uint32_t i)
-    {
-        uint32_t r = i;
-        for (int s = 5; s < K; s += 5)
-            r ^= (i >> s) & 31u;
-        return r;
-    }
+    // LDS slot of tile-local index i (lds_swizzle): thread bits placed on
+    // high tile bits by a re-layout send a wavefront's lanes to different
+    // banks instead of one.
+    static __host__ __device__ __forceinline__ constexpr uint32_t swz(uint32_t i) { return lds_swizzle(i, K); }
 
     // LDS address of the buffer.  The kernels that use TileKernel have no
     // static LDS (checked at launch), so the buffer starts at LDS address 0
@@ -360,45 +427,47 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     }
 
     // element COMP of every amplitude, registers <-> LDS at the tile-local
-    // indices of the layout (tbase, regs, fl)
+    // indices of the layout (tbase, so, fl)
     template <int COMP>
-    static __device__ __forceinline__ void to_lds(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
+    static __device__ __forceinline__ void to_lds(unsigned char *lds, C (&v)[NR], uint32_t tbase, const SlotOffs &so,
                                                    uint32_t fl)
     {
         uint32_t fo = 0;  // the flipped slot bits of the pattern
 #pragma unroll
         for (int s = 0; s < LOG_R; ++s)
-            fo ^= ((fl >> s) & 1u) ? swz(1u << rbit(regs, s)) * EB : 0u;
+            fo ^= ((fl >> s) & 1u) ? so.o[s] : 0u;
         const uint32_t tb = lds_base(lds) ^ (swz(tbase) * EB) ^ fo;
-        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * EB; },
+        for_slots<uint32_t>([&](int s) { return so.o[s]; },
                             [&](int j, uint32_t o) { put<COMP>(tb ^ o, v[j]); });
     }
     template <int COMP>
-    static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs)
+    static __device__ __forceinline__ void from_lds(const unsigned char *lds, C (&v)[NR], uint32_t tbase,
+                                                     const SlotOffs &so)
     {
         const uint32_t tb = lds_base(lds) ^ (swz(tbase) * EB);
-        for_slots<uint32_t>([&](int s) { return swz(1u << rbit(regs, s)) * EB; },
+        for_slots<uint32_t>([&](int s) { return so.o[s]; },
                             [&](int j, uint32_t o) { get<COMP>(tb ^ o, v[j]); });
     }
 
-    // Re-layout (tbase, regs, fl) -> (tbase2, regs2, no flips) through LDS,
-    // one component per round with HALF.
-    static __device__ __forceinline__ void relayout(unsigned char *lds, C (&v)[NR], uint32_t tbase, uint32_t regs,
-                                                    uint32_t fl, uint32_t tbase2, uint32_t regs2)
+    // Re-layout (tbase, so, fl) -> (tbase2, so2, no flips) through LDS, one
+    // component per round with HALF.
+    static __device__ __forceinline__ void relayout(unsigned char *lds, C (&v)[NR], uint32_t tbase,
+                                                    const SlotOffs &so, uint32_t fl, uint32_t tbase2,
+                                                    const SlotOffs &so2)
     {
         if constexpr (HALF) {
-            to_lds<0>(lds, v, tbase, regs, fl);
+            to_lds<0>(lds, v, tbase, so, fl);
             lds_sync();
-            from_lds<0>(lds, v, tbase2, regs2);
+            from_lds<0>(lds, v, tbase2, so2);
             lds_sync();
-            to_lds<1>(lds, v, tbase, regs, fl);
+            to_lds<1>(lds, v, tbase, so, fl);
             lds_sync();
-            from_lds<1>(lds, v, tbase2, regs2);
+            from_lds<1>(lds, v, tbase2, so2);
             lds_sync();
         } else {
-            to_lds<2>(lds, v, tbase, regs, fl);
+            to_lds<2>(lds, v, tbase, so, fl);
             lds_sync();
-            from_lds<2>(lds, v, tbase2, regs2);
+            from_lds<2>(lds, v, tbase2, so2);
             lds_sync();
         }
     }
@@ -408,23 +477,45 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     // the fields of one operation, read together (scalar registers)
     struct OpV {
         int32_t kind, slot;
-        uint32_t rmask, lmask, tlane;
+        uint32_t rmask, lmask, tlane, aux;
         uint64_t hmask, hbit;
         double m[8];
+        uint32_t w[6];  // the first words of m (OP_REMAP: LDS slots of the new layout's slot bits)
     };
+    // The record as three wide scalar loads (64 + 32 + 8 bytes) issued
+    // together, so that one wait covers the whole operation.
+    using U16 = uint32_t __attribute__((ext_vector_type(16)));
+    using U8 = uint32_t __attribute__((ext_vector_type(8)));
+    using U2 = uint32_t __attribute__((ext_vector_type(2)));
     static __device__ __forceinline__ OpV fetch(OpPtr ops, int i)
     {
+        using CP = const __attribute__((address_space(4))) unsigned char *;
+        const CP p = (CP)(ops + i);
+        const U16 a = *(const __attribute__((address_space(4))) U16 *)p;
+        const U8 b = *(const __attribute__((address_space(4))) U8 *)(p + 64);
+        const U2 c = *(const __attribute__((address_space(4))) U2 *)(p + 96);
+        __asm__ __volatile__("" ::"s"(a), "s"(b), "s"(c));
+        auto d = [](uint32_t lo, uint32_t hi) { return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32)); };
         OpV o;
-        o.kind = ops[i].kind;
-        o.slot = ops[i].slot;
-        o.rmask = ops[i].rmask;
-        o.lmask = ops[i].lmask;
-        o.tlane = ops[i].tlane;
-        o.hmask = ops[i].hmask;
-        o.hbit = ops[i].hbit;
+        o.kind = (int32_t)a[0];
+        o.slot = (int32_t)a[1];
+        o.rmask = a[2];
+        o.lmask = a[3];
+        o.tlane = a[4];
+        o.aux = a[5];
+        o.hmask = (uint64_t)a[6] | ((uint64_t)a[7] << 32);
+        o.hbit = (uint64_t)a[8] | ((uint64_t)a[9] << 32);
+        o.m[0] = d(a[10], a[11]);
+        o.m[1] = d(a[12], a[13]);
+        o.m[2] = d(a[14], a[15]);
+        o.m[3] = d(b[0], b[1]);
+        o.m[4] = d(b[2], b[3]);
+        o.m[5] = d(b[4], b[5]);
+        o.m[6] = d(b[6], b[7]);
+        o.m[7] = d(c[0], c[1]);
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            o.m[q] = ops[i].m[q];
+        for (int q = 0; q < 6; ++q)
+            o.w[q] = a[10 + q];
         return o;
     }
 
@@ -505,43 +596,59 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
                 load(w, t + t_step);
             const uint64_t base = tile_base(a, t);
 
-            uint32_t regs = 0, tbase = 0, fl = 0;
+            SlotOffs so = offs_plain();
+            uint32_t tbase = 0, fl = 0;
             bool have = false;
             int oi = 0;
             if (dload) {
-                regs = ops[0].rmask;
-                tbase = lane_bits(ops[0].hbit, tid);
+                const OpV first = fetch(ops, 0);
+                so = offs_of(first.w);
+                tbase = lane_bits(first.hbit, tid);
                 have = true;
                 oi = 1;
             } else if (n_ops > 0) {
                 // loaded in the plain layout; the first OP_REMAP moves it
-                regs = regs_plain();
                 tbase = tid;
                 have = true;
             }
 
             for (; oi < n_ops; ++oi) {
                 const OpV cur = fetch(ops, oi);
-                // issue all of the operation's scalar loads together, so that
-                // one wait covers them
-                __asm__ __volatile__("" ::"s"(cur.kind), "s"(cur.hmask), "s"(cur.m[0]), "s"(cur.m[7]));
                 const int kind = cur.kind;
-                if (kind == OP_REMAP) {
-                    const uint32_t regs2 = cur.rmask, tbase2 = lane_bits(cur.hbit, tid);
-                    relayout(lds, v, tbase, regs, fl, tbase2, regs2);
-                    regs = regs2;
+                // the most frequent operations first: shears have no controls
+                static_assert((OP_SHEAR | 2) == OP_SHEAR2, "one test for both shear records");
+                if ((kind | 2) == OP_SHEAR2) {
+                    const int slot = cur.slot;
+                    fl ^= cur.tlane ? 1u << slot : 0u;
+                    dispatch_shear(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1], (R)cur.m[2], (R)cur.m[3]);
+                    if (kind == OP_SHEAR2) {
+                        const int s2 = (int)(cur.aux & 255u);
+                        fl ^= (cur.aux >> 8) ? 1u << s2 : 0u;
+                        dispatch_shear(s2, (fl >> s2) & 1u, v, (R)cur.m[4], (R)cur.m[5], (R)cur.m[6], (R)cur.m[7]);
+                    }
+                } else if (kind == OP_REMAP) {
+                    const SlotOffs so2 = offs_of(cur.w);
+                    const uint32_t tbase2 = lane_bits(cur.hbit, tid);
+                    relayout(lds, v, tbase, so, fl, tbase2, so2);
+                    so = so2;
                     tbase = tbase2;
                     fl = 0;
+                } else if (kind == OP_LSWAP) {
+                    // slot bit `slot` <-> lane bit tlane; the tile bit lmask
+                    // moves into the slot, the tile bit rmask onto the lane
+                    const int slot = cur.slot;
+                    dispatch_lane_swap(slot, cur.tlane == 5, (fl >> slot) & 1u, v);
+                    tbase = (tbase & ~cur.lmask) | (((tid >> cur.tlane) & 1u) ? cur.rmask : 0u);
+                    const uint32_t o_new = offs_of(cur.w).o[0];
+#pragma unroll
+                    for (int q = 0; q < LOG_R; ++q)
+                        so.o[q] = q == slot ? o_new : so.o[q];
                 } else if ((base & cur.hmask) == cur.hmask) {
                     const uint32_t rm = cur.rmask, lm = cur.lmask;
                     const uint32_t rv = rm & ~fl;
                     const bool lp = (tbase & lm) == lm;
                     const int slot = cur.slot;
-                    if (kind == OP_SHEAR) {
-                        fl ^= cur.tlane ? 1u << slot : 0u;
-                        dispatch_shear(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1], (R)cur.m[2],
-                                       (R)cur.m[3]);
-                    } else if (kind == OP_PHASE) {
+                    if (kind == OP_PHASE) {
                         dispatch_phase(slot, (fl >> slot) & 1u, v, (R)cur.m[0], (R)cur.m[1]);
                     } else if (kind == OP_U) {
                         Mat<R> m;
@@ -618,7 +725,7 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
                 for (int j = 0; j < NR; ++j)
                     v[j].y = *at(rl ^ (swz((uint32_t)j << LOG_NT) * RB));
             } else if (have && !dstore) {
-                relayout(lds, v, tbase, regs, fl, tid, regs_plain());
+                relayout(lds, v, tbase, so, fl, tid, offs_plain());
             }
             uint64_t dfl = 0;
             if (direct) {

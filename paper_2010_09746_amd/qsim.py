@@ -288,7 +288,7 @@ def qs_program_get_stats(h: int) -> dict:
 
 
 OPC_NAMES = ["tile_pass", "u", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch", "plain_u",
-             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction", "shear", "phase"]
+             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction", "shear", "phase", "lswap"]
 
 
 def qs_program_op_counts(h: int) -> dict:

@@ -50,6 +50,10 @@ def test_reduced_one_qubit_form_counts():
     assert b["u"] == n_u and b["shear"] == 0 and b["phase"] == 0
     # every one-qubit gate is either two shears or whole; the last one of each qubit is whole
     assert a["shear"] + a["u"] == n_u and a["u"] >= 20 and a["shear"] > 4 * a["u"]
+    # a qubit whose next two-qubit gate makes it a CNOT target keeps a I + b X
+    # pending (it commutes with the target), one that acts as a control or in a
+    # CZ keeps diag(1, z): no pending factor is applied on its own
+    assert a["phase"] == 0
 
 
 def test_gate_record_layout():

@@ -1,13 +1,14 @@
 """The reduced one-qubit update (each uncontrolled gate M of a tile pass as
-M00 diag(1, z) L(q) U(p), two in-place shears, with diag(1, z) kept pending
-on the qubit and M00 in one scalar) against the whole-matrix form and the
-oracle, on every path that has to settle a pending diagonal: CNOT and
-controlled-gate targets inside a pass, targets whose shears ended an earlier
-pass, gates run as launches of their own (fusion without the pass, and the
-fallback of Algorithm 1 when no exchange is allowed), gates whose larger
-first-row entry is off the diagonal (an exchange first), singular and
-non-unitary matrices, long programs whose scalar has to be taken by a whole
-gate, and the last gate of each qubit."""
+two in-place shears L(q) U(p) with a left factor kept pending on the qubit:
+M00 diag(1, z), M00 moved into one scalar, or a I + b X when the qubit's next
+operations are CNOT targets) against the whole-matrix form and the oracle, on
+every path that has to settle a pending factor: controlled-gate targets
+inside a pass, targets whose shears ended an earlier pass, gates run as
+launches of their own (fusion without the pass, and the fallback of
+Algorithm 1 when no exchange is allowed), gates whose larger first-row entry
+is off the diagonal (an exchange first), singular and non-unitary matrices,
+long programs whose scalar has to be taken by a whole gate, and the last gate
+of each qubit; and the a I + b X form through CNOT and span{I, X} targets."""
 
 import sys
 
@@ -62,17 +63,79 @@ def test_reduced_equals_whole_matrices_and_oracle(dt, k, r, pinned, perm_exec):
     assert np.abs(b - ref).max() <= TOL[dt]
 
 
+def _layers(n, layers, seed, two_qubit):
+    """Haar U(2) on every qubit, then two_qubit(rng, c, t, layer) on a random
+    perfect matching, per layer."""
+    rng = np.random.default_rng(seed)
+    recs = []
+    for layer in range(layers):
+        for q in range(n):
+            recs.append((KIND_U, q, -1, haar_u2(rng)))
+        perm = rng.permutation(n)
+        for i in range(0, n - 1, 2):
+            recs.extend(two_qubit(rng, int(perm[i]), int(perm[i + 1]), layer))
+    return recs
+
+
 def test_pending_phase_settled_across_passes():
-    """Small tiles and bundles of one exchange: many CNOT targets meet a
-    pending diagonal left by shears of an earlier pass (applied on its own)."""
+    """Small tiles and bundles of one exchange: controlled Haar gates' targets
+    meet a pending diagonal left by shears of an earlier pass (applied on its
+    own)."""
     n = 14
     _say("pending phases across passes")
-    g = layered_circuit(n, 30, seed=77)
+    g = make_gates(_layers(n, 30, 77, lambda rng, c, t, layer: [(KIND_CU, c, t, haar_u2(rng))]))
     opts = dict(form="pass", k_tile=8, max_swaps=1, pinned=3, perm_exec="relabel")
     P = Q.Program(g, n, "c128", **opts)
-    assert P.op_counts()["phase"] > 0
+    assert P.op_counts()["phase"] > 50
     P.close()
     assert np.abs(_run(g, n, "c128", **opts) - O.run(g, n)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_pending_factor_commuting_with_cnot_targets(dt):
+    """A qubit whose next operations are CNOT targets (or targets of
+    controlled gates in span{I, X}) keeps a I + b X pending: it commutes with
+    them, so no pending factor is applied on its own.  Exchange gates on the
+    targets absorb it; such a gate commutes with the CNOT target before it and
+    may be scheduled first, and the target then meets the exchange gate's own
+    diagonal factor (applied on its own).  Against the oracle and the
+    whole-matrix form."""
+    n = 14
+    _say(f"a I + b X pending factors {dt}")
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+
+    def circuit(exchanges):
+        def two(rng, c, t, layer):
+            out = []
+            if layer % 3 == 2:
+                th = rng.uniform(0, 6.283)
+                out.append((KIND_CU, c, t, np.array([[np.cos(th), 1j * np.sin(th)], [1j * np.sin(th), np.cos(th)]])))
+            else:
+                out.append((KIND_CX, c, t, None))
+            if exchanges and layer % 5 == 4:
+                out.append((KIND_U, t, -1, X))
+            return out
+        return make_gates(_layers(n, 24, 11, two))
+
+    opts = dict(form="pass", k_tile=10, max_swaps=8, pinned=3, perm_exec="relabel")
+    counts = {}
+    for ex in (False, True):
+        P = Q.Program(circuit(ex), n, dt, **opts)
+        counts[ex] = P.op_counts()
+        P.close()
+    g = circuit(True)
+    n_u = int(sum(1 for k in g["kind"] if k == KIND_U))
+    n_x = int(sum(1 for i in range(len(g)) if g["kind"][i] == KIND_U and g["u"][i][0] == 0 and g["u"][i][1] == 0))
+    assert counts[False]["phase"] == 0
+    assert counts[True]["phase"] <= n_x and counts[True]["shear"] > 0.8 * (n_u - n_x)
+    ref = O.run(g, n)
+    a = _run(g, n, dt, **opts)
+    b = _run(g, n, dt, full_matrices=True, **opts)
+    assert np.abs(a - ref).max() <= TOL[dt]
+    assert np.abs(b - ref).max() <= TOL[dt]
+    if dt == "c64":
+        fid = abs(np.vdot(ref, a)) ** 2 / np.vdot(a, a).real
+        assert 1 - fid <= 1e-6
 
 
 @pytest.mark.parametrize("r,pinned", [(0, 0), (2, 9)])
