@@ -467,11 +467,16 @@ def ablation(a):
 def costmodel_form(a):
     """Measured cost model: predict every candidate (k, r, register bits) for
     the 30-qubit workload, run a spread of them, and report how well the
-    prediction ranks them and what the predicted choice costs."""
+    prediction ranks them and what the predicted choice costs.  Then the pass
+    deciding by the same measured costs (each PermuteQubits' chain prefix
+    against a gate run on its own) beside Algorithm 1's step function, on the
+    30-qubit workload with relabelled placements and, with the paper's moved
+    placements and single exchanges, on that workload and the paper's random
+    family (p = 1, 28 qubits): predicted and measured device time."""
     import numpy as np
 
-    from paper_2010_09746_amd import costmodel
-    from workloads import config_circuit
+    from paper_2010_09746_amd import costmodel, qsim as Q
+    from workloads import config_circuit, paper_random_circuit
 
     gates = config_circuit(2, n=a.n, layers=a.layers)
     cm = costmodel.CostModel(a.dtype, n_cal=a.cal_n)
@@ -484,12 +489,34 @@ def costmodel_form(a):
     pm = [r["predicted_ms"] for r in pick]
     mm = [r["measured_ms"] for r in pick]
     chosen = pick[0]["measured_ms"]
+    in_pass = []
+    n_rf = a.n - 2
+    cases = [("layered", gates, a.n, dict(best)),
+             ("layered, moved placements, r=1", gates, a.n,
+              dict(k_tile=a.k, max_swaps=1, pinned=0, perm_exec="move", reg_bits=0)),
+             ("random family p=1, moved placements, r=1", paper_random_circuit(n_rf, 30 * n_rf, 1.0, 20100946 + 8),
+              n_rf, dict(k_tile=a.k, max_swaps=1, pinned=0, perm_exec="move", reg_bits=0))]
+    for name, g, n, opts in cases:
+        row = {"workload": name, "n": n, "opts": opts}
+        costs = cm.pass_costs(n, opts["k_tile"], opts["reg_bits"], opts["perm_exec"])
+        for tag, c in (("step", None), ("costed", cm.as_struct(costs))):
+            ms, counts = cm.predict(g, n, costed=c is not None, **opts)
+            P = Q.Program(g, n, a.dtype, form="pass", costs=c, **opts)
+            prog_stats = {k: P.stats()[k] for k in ("n_perm", "n_global", "n_tile_passes")}
+            P.close()
+            row[tag] = dict(predicted_ms=ms, measured_ms=costmodel.measure_ms(g, n, a.dtype, opts, reps=1, costs=c),
+                            **prog_stats)
+        row["pass_costs"] = costs
+        in_pass.append(row)
+        print(f"costed pass, {name}: step {row['step']['measured_ms']:.1f} ms, costed "
+              f"{row['costed']['measured_ms']:.1f} ms", file=sys.stderr, flush=True)
     _study_line("cost-model regret (chosen / best measured)", chosen / min(mm), "x", chosen,
                 {"workload": f"cost model on the layered circuit n={a.n} {a.dtype} ({len(gates)} gates): "
-                             f"{len(table)} candidates predicted, {len(pick)} measured"},
+                             f"{len(table)} candidates predicted, {len(pick)} measured; the pass deciding by "
+                             f"the measured costs against Algorithm 1's step function"},
                 {"chosen": best, "choose_seconds": choose_s, "rank_correlation": costmodel.rank_correlation(pm, mm),
                  "measured": pick, "calibration": {f"k{k}_rb{rb}": v for (k, rb), v in cm.tile_costs.items()},
-                 "launch_costs": cm.launch_costs,
+                 "launch_costs": cm.launch_costs, "in_pass_choices": in_pass,
                  "fit_residual": {f"k{k}_rb{rb}": v for (k, rb), v in cm.fit_residual.items()}},
                 hib=False)
 

@@ -185,6 +185,41 @@ qs_status qs_permute_qubits(qs_state *s, const int *sigma_new);
  * identity).  Host-only; device tables are uploaded on first run. */
 qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt,
                      const int *sigma0, const qs_run_opts *opts, qs_program **out);
+
+/* Measured costs for the pass's own choices (paper, Section 3, closing
+ * remark: a pass may use the simulator's benchmarks instead of the step
+ * function local / global).  All in one time unit, for the state size being
+ * compiled for (bench-measured, e.g. by paper_2010_09746_amd.costmodel):
+ *   tile_pass   fixed cost of one fused tile pass (every amplitude read and
+ *               written once)
+ *   in_pass[c]  cost of one gate inside a tile pass: c = 0 a non-diagonal
+ *               one-qubit gate, 1 a two-qubit gate with a non-diagonal target
+ *               (CX, CU), 2 a diagonal gate (CZ, controlled or one-qubit
+ *               diagonal)
+ *   move        cost of moving every amplitude once (QS_PERM_MOVE: a
+ *               PermuteQubits of P exchanged position pairs moves the fraction
+ *               1 - 2^-P); 0 with relabelled placements
+ *   plain[k]    one gate of kind k (QS_GATE_U, CX, CZ, CU) as a launch of its
+ *               own (the paper's communicating gate) */
+typedef struct {
+    double tile_pass;
+    double in_pass[3];
+    double move;
+    double plain[4];
+} qs_pass_costs;
+
+/* qs_compile with the pass deciding by predicted time (form QS_FORM_PASS,
+ * max_swaps >= 1).  Where Algorithm 1 takes the whole chain of exchanges that
+ * raise its count, and falls back to one communicating gate only when no
+ * exchange helps, this pass predicts, at each PermuteQubits, the time per
+ * gate of every prefix of that chain (the permutation's data movement, the
+ * tile pass and its gates) and of running the first ready gate as a launch
+ * of its own, and takes the cheapest; ties keep Algorithm 1's choice.  With
+ * no movement or in-pass costs and plain launches costlier than a tile pass
+ * it emits exactly qs_compile's instructions.  costs: host, read during the call; negative or non-finite
+ * entries give QS_ERR_ARG.  Otherwise as qs_compile. */
+qs_status qs_compile_costed(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
+                            const qs_run_opts *opts, const qs_pass_costs *costs, qs_program **out);
 qs_status qs_program_destroy(qs_program *p);
 qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
 /* Work of a compiled program by class, for a cost model that prices each

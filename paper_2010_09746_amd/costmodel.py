@@ -19,6 +19,12 @@ tile), the other in-pass classes are per operation and tile weight, and the
 one-gate and data-movement launches have their own per-launch costs.  The
 costs are fitted by least squares from small calibration passes at n_cal
 qubits, one per class, whose work counts come from the same compiler.
+
+The same costs can also drive the pass's own choices (``pass_costs``, used by
+``qsim.Program(costs=...)`` / ``qs_compile_costed``): at each PermuteQubits it
+prices every prefix of Algorithm 1's chain of exchanges (data movement, tile
+pass, gates) per gate against running the first ready gate as a launch of its
+own, and ``choose`` can consider those programs beside the step-function ones.
 """
 
 from __future__ import annotations
@@ -175,20 +181,49 @@ class CostModel:
                                                "move_fraction"))
         return ms * scale
 
-    def predict(self, gates, n: int, **opts) -> tuple:
-        prog = Q.Program(gates, n, self.dtype, form="pass", **opts)
+    def pass_costs(self, n: int, k: int, reg_bits: int = 0, perm_exec: str = "relabel") -> dict:
+        """The calibrated costs in the form the pass's own choices use
+        (qs_pass_costs, ms at n qubits): a tile pass (its fixed cost plus the
+        four re-layouts a pass of the layered workload makes), a gate inside
+        it by class (non-diagonal one-qubit: a shear; two-qubit with a
+        non-diagonal target: the mean of register- and lane-controlled
+        exchanges; diagonal: a sign flip), moving the whole state (moved
+        placements only) and each gate kind as a launch of its own."""
+        self.calibrate([(k, reg_bits)])
+        scale = 2.0 ** (n - self.n_cal)
+        tc, lc = self.tile_costs[(k, reg_bits)], self.launch_costs
+        return dict(tile=scale * (tc["tile_pass"] + 4 * tc["remap"]),
+                    **{"in": (scale * tc["shear"], scale * 0.5 * (tc["x_reg"] + tc["x_lane"]), scale * tc["neg"])},
+                    move=scale * lc["move_fraction"] if perm_exec == "move" else 0.0,
+                    plain=tuple(scale * lc[c] for c in ("plain_u", "plain_cx", "plain_cz", "plain_cu")))
+
+    @staticmethod
+    def as_struct(c: dict):
+        return Q.make_pass_costs(c["tile"], c["in"], c["move"], c["plain"])
+
+    def predict(self, gates, n: int, costed: bool = False, **opts) -> tuple:
+        costs = None
+        if costed:
+            costs = self.as_struct(self.pass_costs(n, opts.get("k_tile", 10), opts.get("reg_bits", 0),
+                                                   opts.get("perm_exec", "relabel")))
+        prog = Q.Program(gates, n, self.dtype, form="pass", costs=costs, **opts)
         counts = prog.op_counts()
         prog.close()
         return self.predict_counts(counts, n, opts.get("k_tile", 10), opts.get("reg_bits", 0)), counts
 
     def choose(self, gates, n: int, ks=(9, 10, 11, 12, 13), rs=(1, 4, 8, 16), reg_bits=(0,),
-               perm_execs=("relabel",)) -> tuple:
-        """Predicted-best options for this circuit and the table of predictions."""
+               perm_execs=("relabel",), costed=(False,)) -> tuple:
+        """Predicted-best options for this circuit and the table of predictions
+        (costed=(False, True) also considers the pass deciding by the
+        measured costs; its entries carry costed=True)."""
         cands = []
-        for k, r, rb, pe in itertools.product(ks, rs, reg_bits, perm_execs):
+        for k, r, rb, pe, cp in itertools.product(ks, rs, reg_bits, perm_execs, costed):
             if k > n or (16 if self.dtype == "c128" else 8) << k > 131072:
                 continue
-            cands.append(dict(k_tile=k, max_swaps=r, reg_bits=rb, perm_exec=pe, pinned=self.pinned))
+            c = dict(k_tile=k, max_swaps=r, reg_bits=rb, perm_exec=pe, pinned=self.pinned)
+            if cp:
+                c["costed"] = True
+            cands.append(c)
         self.calibrate({(c["k_tile"], c["reg_bits"]) for c in cands})
         table = []
         for c in cands:
@@ -198,10 +233,11 @@ class CostModel:
         return table[0]["opts"], table
 
 
-def measure_ms(gates, n: int, dtype: str, opts: dict, reps: int = 2) -> float:
-    """Device time of the pass form of a circuit with the given options."""
+def measure_ms(gates, n: int, dtype: str, opts: dict, reps: int = 2, costs=None) -> float:
+    """Device time of the pass form of a circuit with the given options (and,
+    with costs, the pass deciding by them)."""
     st = Q.State(n, dtype)
-    prog = Q.Program(gates, n, dtype, form="pass", **opts)
+    prog = Q.Program(gates, n, dtype, form="pass", costs=costs, **opts)
     ms = _pass_ms(st, prog, reps=reps)
     prog.close()
     st.close()

@@ -621,8 +621,9 @@ qs_status qs_permute_qubits(qs_state *s, const int *sigma_new)
     });
 }
 
-qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
-                     const qs_run_opts *opts, qs_program **out)
+namespace {
+qs_status compile_entry(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
+                        const qs_run_opts *opts, const qs_pass_costs *costs, qs_program **out)
 {
     return guard([&] {
         need(out != nullptr, "out is NULL");
@@ -638,15 +639,36 @@ qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, 
         qs_run_opts o = opts ? *opts : default_opts();
         if (o.form == QS_FORM_PASS)
             need(o.k_tile >= 1, "k_tile must be >= 1");
+        if (costs) {
+            const double v[] = {costs->tile_pass, costs->in_pass[0], costs->in_pass[1], costs->in_pass[2],
+                                costs->move, costs->plain[0], costs->plain[1], costs->plain[2], costs->plain[3]};
+            for (double x : v)
+                need(std::isfinite(x) && x >= 0.0, "pass costs must be finite and non-negative");
+        }
         auto *p = new qs_program();
         try {
-            compile_program(gates, n_gates, n, dt, sigma0, o, p->p);
+            compile_program(gates, n_gates, n, dt, sigma0, o, p->p, {}, costs);
         } catch (...) {
             delete p;
             throw;
         }
         *out = p;
     });
+}
+}  // namespace
+
+qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
+                     const qs_run_opts *opts, qs_program **out)
+{
+    return compile_entry(gates, n_gates, n, dt, sigma0, opts, nullptr, out);
+}
+
+qs_status qs_compile_costed(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
+                            const qs_run_opts *opts, const qs_pass_costs *costs, qs_program **out)
+{
+    return guard([&] { need(costs != nullptr, "costs is NULL"); }) == QS_OK
+               ? compile_entry(gates, n_gates, n, dt, sigma0, opts, costs, out)
+               : QS_ERR_ARG;
 }
 
 qs_status qs_program_destroy(qs_program *p)

@@ -179,10 +179,11 @@ public:
 
     // Number of not-scheduled gates that become schedulable under sigma;
     // optionally collects the non-diagonal targets (qubits) of gates that are
-    // reached (all predecessors done or counted) but are not local.
+    // reached (all predecessors done or counted) but are not local, and the
+    // counted gates by cost class (gate_class).
     // The closure does not depend on the order gates are visited in, so a
     // plain work list replaces the program-order heap of sweep().
-    int64_t closure(const int *sigma, std::vector<char> *reach_targets)
+    int64_t closure(const int *sigma, std::vector<char> *reach_targets, int64_t *classes = nullptr)
     {
         work_.assign(frontier_.begin(), frontier_.end());
         touched_.clear();
@@ -196,6 +197,8 @@ public:
                 continue;
             }
             ++cnt;
+            if (classes)
+                ++classes[gate_class(gi_[v])];
             for (int s : d_.succ[v]) {
                 if (tmp_[s] < 0) {
                     tmp_[s] = npend_[s];
@@ -209,6 +212,13 @@ public:
             tmp_[s] = -1;
         return cnt;
     }
+
+    // qs_pass_costs::in_pass class: 0 non-diagonal one-qubit, 1 two-qubit
+    // with a non-diagonal target, 2 diagonal
+    static int gate_class(const GateInfo &gi) { return gi.target < 0 ? 2 : gi.nq == 1 ? 0 : 1; }
+
+    // lowest-index ready gate (Algorithm 1 fallback), not scheduled
+    int first_ready() const { return *std::min_element(frontier_.begin(), frontier_.end()); }
 
     // lowest-index ready gate (Algorithm 1 fallback); schedules it
     int take_first_ready()
@@ -248,9 +258,14 @@ private:
 
 // One iteration at a time: apply every ready local gate, then insert one
 // PermuteQubits (or, when no exchange helps, run one gate as global).
-PassRunner::PassRunner(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned, const std::vector<int> &sigma0)
+PassRunner::PassRunner(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned, const std::vector<int> &sigma0,
+                       const qs_pass_costs *costs)
     : n_(n), m_(m), r_(r), pinned_(pinned), gi_(ng), sigma_(sigma0)
 {
+    if (costs) {
+        costed_ = true;
+        costs_ = *costs;
+    }
     for (int64_t v = 0; v < ng; ++v)
         gi_[v] = analyse(g[v]);
     dag_ = build_dag(g, gi_, n);
@@ -273,10 +288,13 @@ bool PassRunner::step(std::vector<Instr> &out)
     if (ps.remaining() == 0)
         return false;
 
+    // the chain of Algorithm 1's exchanges (each strictly raising the count),
+    // with the placement and count after each link
     std::vector<int> cur = sigma_, cand(n), best(n);
     std::vector<char> targets(n);
+    std::vector<std::vector<int>> prefix;
+    std::vector<int64_t> counts;
     int64_t base = 0;
-    int swaps = 0;
     for (int step = 0; step < r_; ++step) {
         std::fill(targets.begin(), targets.end(), 0);
         ps.closure(cur.data(), &targets);
@@ -303,13 +321,41 @@ bool PassRunner::step(std::vector<Instr> &out)
             break;
         cur = best;
         base = best_a;
-        ++swaps;
+        prefix.push_back(cur);
+        counts.push_back(best_a);
     }
-    if (swaps > 0) {
-        sigma_ = cur;
+    // Algorithm 1 takes the whole chain, or the fallback gate when it is empty
+    int take = (int)prefix.size();
+    if (costed_ && !prefix.empty()) {
+        // predicted time per gate of each prefix: the permutation's data
+        // movement, the tile pass and its gates; against the first ready gate
+        // as a launch of its own.  Ties keep the longer chain, then the chain.
+        double best_rate = 0.0;
+        for (int b = (int)prefix.size(); b >= 1; --b) {
+            int64_t cls[3] = {0, 0, 0};
+            const int64_t a = ps.closure(prefix[b - 1].data(), nullptr, cls);
+            int changed = 0;
+            for (int q = 0; q < n; ++q)
+                changed += prefix[b - 1][q] != sigma_[q];
+            const double t = costs_.move * (1.0 - std::ldexp(1.0, -(changed / 2))) + costs_.tile_pass +
+                             cls[0] * costs_.in_pass[0] + cls[1] * costs_.in_pass[1] + cls[2] * costs_.in_pass[2];
+            const double rate = t / (double)std::max<int64_t>(a, 1);
+            if (b == (int)prefix.size() || rate < best_rate) {
+                best_rate = rate;
+                take = b;
+            }
+        }
+        const int v = ps.first_ready();
+        const int kind = gi_[v].kind;
+        const double plain = costs_.plain[kind >= 0 && kind < 4 ? kind : 0];
+        if (plain < best_rate)
+            take = 0;
+    }
+    if (take > 0) {
+        sigma_ = prefix[take - 1];
         out.push_back(Instr{1, -1, sigma_});
         ++stats_.n_perm;
-        stats_.n_swaps += swaps;
+        stats_.n_swaps += take;
     } else {
         int v = ps.take_first_ready();
         out.push_back(Instr{2, v, {}});
@@ -1074,7 +1120,8 @@ void tile_args_identity(int k, int log_nt, int log_r, TileArgs &a)
 }
 
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0_in,
-                     const qs_run_opts &o, Program &p, const std::function<void(Program &)> &progress)
+                     const qs_run_opts &o, Program &p, const std::function<void(Program &)> &progress,
+                     const qs_pass_costs *costs)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (n < 1 || n > MAX_COMPILE_QUBITS)
@@ -1249,7 +1296,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         };
         // the pass and the lowering advance together, so a caller can start
         // the first launches while later permutations are still being chosen
-        PassRunner pr(g, ng, n, k, o.max_swaps, o.pinned, p.sigma0);
+        PassRunner pr(g, ng, n, k, o.max_swaps, o.pinned, p.sigma0, costs);
         bool more = true;
         while (more) {
             more = pr.step(p.instrs);

@@ -131,9 +131,12 @@ struct Dag {
 // The same pass, one iteration per step(): the instructions of the sweep and
 // the PermuteQubits (or global gate) that follows it are appended to out;
 // false once every gate is scheduled.
+// With costs, each PermuteQubits (or the fallback gate) is chosen by
+// predicted time per gate instead (see qs_compile_costed).
 class PassRunner {
 public:
-    PassRunner(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned, const std::vector<int> &sigma0);
+    PassRunner(const qs_gate *g, int64_t ng, int n, int m, int r, int pinned, const std::vector<int> &sigma0,
+               const qs_pass_costs *costs = nullptr);
     ~PassRunner();
     PassRunner(const PassRunner &) = delete;
     PassRunner &operator=(const PassRunner &) = delete;
@@ -143,6 +146,8 @@ public:
 
 private:
     int n_, m_, r_, pinned_;
+    bool costed_ = false;
+    qs_pass_costs costs_{};
     std::vector<GateInfo> gi_;
     Dag dag_;
     PassState *ps_ = nullptr;
@@ -168,7 +173,8 @@ struct Program {
 // iteration, once the launches of every completed segment are in p.launches
 // (and their operations in p.ops); launches already there never change.
 void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int *sigma0,
-                     const qs_run_opts &o, Program &p, const std::function<void(Program &)> &progress = {});
+                     const qs_run_opts &o, Program &p, const std::function<void(Program &)> &progress = {},
+                     const qs_pass_costs *costs = nullptr);
 
 }  // namespace qsim
 

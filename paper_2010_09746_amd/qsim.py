@@ -47,7 +47,7 @@ EXPORTS = [
     "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_plan",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
     "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
-    "qs_run_program_noalloc",
+    "qs_run_program_noalloc", "qs_compile_costed",
 ]
 
 
@@ -61,6 +61,22 @@ class qs_run_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("k_tile", ctypes.c_int32), ("max_swaps", ctypes.c_int32),
                 ("pinned", ctypes.c_int32), ("perm_exec", ctypes.c_int32), ("max_fuse", ctypes.c_int32),
                 ("reg_bits", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class qs_pass_costs(ctypes.Structure):
+    _fields_ = [("tile_pass", ctypes.c_double), ("in_pass", ctypes.c_double * 3), ("move", ctypes.c_double),
+                ("plain", ctypes.c_double * 4)]
+
+
+def make_pass_costs(tile_pass, in_pass, move, plain) -> qs_pass_costs:
+    c = qs_pass_costs()
+    c.tile_pass = tile_pass
+    c.move = move
+    for i in range(3):
+        c.in_pass[i] = in_pass[i]
+    for i in range(4):
+        c.plain[i] = plain[i]
+    return c
 
 
 class qs_program_stats(ctypes.Structure):
@@ -124,6 +140,8 @@ def load() -> ctypes.CDLL:
     L.qs_permute_qubits.argtypes = [_vp, _ip]
     L.qs_compile.argtypes = [_vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _ip,
                              ctypes.POINTER(qs_run_opts), ctypes.POINTER(_vp)]
+    L.qs_compile_costed.argtypes = [_vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _ip,
+                                    ctypes.POINTER(qs_run_opts), ctypes.POINTER(qs_pass_costs), ctypes.POINTER(_vp)]
     L.qs_program_destroy.argtypes = [_vp]
     L.qs_program_get_stats.argtypes = [_vp, ctypes.POINTER(qs_program_stats)]
     L.qs_program_op_counts.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
@@ -274,6 +292,17 @@ def qs_compile(gates, n: int, dtype, sigma0=None, opts: qs_run_opts | None = Non
     s0 = _ints(sigma0).ctypes.data_as(_ip) if sigma0 is not None else None
     _chk(load().qs_compile(g.ctypes.data, len(g), n, _dtype_code(dtype), s0,
                            ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
+    return h.value
+
+
+def qs_compile_costed(gates, n: int, dtype, sigma0=None, opts: qs_run_opts | None = None,
+                      costs: qs_pass_costs | None = None) -> int:
+    g = as_gates(gates)
+    h = _vp()
+    s0 = _ints(sigma0).ctypes.data_as(_ip) if sigma0 is not None else None
+    _chk(load().qs_compile_costed(g.ctypes.data, len(g), n, _dtype_code(dtype), s0,
+                                  ctypes.byref(opts) if opts is not None else None,
+                                  ctypes.byref(costs) if costs is not None else None, ctypes.byref(h)))
     return h.value
 
 
@@ -596,9 +625,12 @@ class State:
 class Program:
     """A compiled circuit (pass of Section 3 + lowering to launches)."""
 
-    def __init__(self, gates, n: int, dtype="c128", sigma0=None, **opts):
+    def __init__(self, gates, n: int, dtype="c128", sigma0=None, costs: qs_pass_costs | None = None, **opts):
         self.n = n
-        self.h = qs_compile(gates, n, dtype, sigma0, make_opts(**opts))
+        if costs is None:
+            self.h = qs_compile(gates, n, dtype, sigma0, make_opts(**opts))
+        else:
+            self.h = qs_compile_costed(gates, n, dtype, sigma0, make_opts(**opts), costs)
 
     def stats(self) -> dict:
         return qs_program_get_stats(self.h)

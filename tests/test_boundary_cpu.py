@@ -213,3 +213,169 @@ def test_relayouts_bounded_on_layered_workload():
     assert c["tile_pass"] == st["n_tile_passes"] == 43
     assert 40 * 3 <= c["remap"] <= 172      # 12 local targets per layer, 4 register bits
     assert c["remap"] == st["n_remaps"]
+
+
+# ----------------------------------------------------------------------------
+# The pass deciding by predicted time (qs_compile_costed; paper, Section 3,
+# closing remark: a pass may use the simulator's benchmarks)
+
+def _is_local(rec, sigma, m):
+    k, q0, q1 = int(rec["kind"]), int(rec["q0"]), int(rec["q1"])
+    u = rec["u"]
+    diag = u[2] == 0 and u[3] == 0 and u[4] == 0 and u[5] == 0
+    if k == KIND_U:
+        return diag or sigma[q0] < m
+    if k == 2:  # CZ
+        return True
+    if k == 3 and diag:  # controlled diagonal
+        return True
+    return sigma[q1] < m
+
+
+def _cost_class(rec):
+    k, u = int(rec["kind"]), rec["u"]
+    diag = u[2] == 0 and u[3] == 0 and u[4] == 0 and u[5] == 0
+    if k == 2 or (k in (0, 3) and diag):
+        return 2
+    return 0 if k == KIND_U else 1
+
+
+def _closure_set(g, preds, done, sigma, m):
+    mark = set()
+    for v in range(len(g)):
+        if v not in done and _is_local(g[v], sigma, m) and all(h in done or h in mark for h in preds[v]):
+            mark.add(v)
+    return mark
+
+
+def _expected_decision(g, preds, done, sigma, m, r, pinned, costs):
+    """Brute force of the decision: Algorithm 1's chain (first strict maximum
+    over local qubits l, then global g, in ascending qubit order; each link
+    strictly raises the count), every prefix priced as movement + tile pass +
+    its gates per gate, against the first ready gate as a launch of its own."""
+    n = len(sigma)
+    prefixes, cur, base = [], list(sigma), 0
+    for _ in range(r):
+        best, arg = base, None
+        for a in range(n):
+            if not (pinned <= cur[a] < m):
+                continue
+            for b in range(n):
+                if cur[b] >= m:
+                    s2 = list(cur)
+                    s2[a], s2[b] = cur[b], cur[a]
+                    c = len(_closure_set(g, preds, done, s2, m))
+                    if c > best:
+                        best, arg = c, s2
+        if arg is None:
+            break
+        cur, base = arg, best
+        prefixes.append(cur)
+    ready = [v for v in range(len(g)) if v not in done and preds[v] <= done]
+    first = min(ready)
+    if not prefixes:
+        return ("global", first)
+    rates = []
+    for p in prefixes:
+        s = _closure_set(g, preds, done, p, m)
+        cls = [0, 0, 0]
+        for v in s:
+            cls[_cost_class(g[v])] += 1
+        changed = sum(1 for q in range(n) if p[q] != sigma[q])
+        t = costs["move"] * (1 - 2.0 ** -(changed // 2)) + costs["tile"] + sum(c * w for c, w in zip(cls, costs["in"]))
+        rates.append(t / len(s))
+    take = len(prefixes)
+    for b in range(len(prefixes), 0, -1):
+        if rates[b - 1] < rates[take - 1]:
+            take = b
+    if costs["plain"][int(g[first]["kind"])] < rates[take - 1]:
+        return ("global", first)
+    return ("perm", tuple(prefixes[take - 1]))
+
+
+def _pc(c):
+    return Q.make_pass_costs(c["tile"], c["in"], c["move"], c["plain"])
+
+
+def test_costed_pass_is_algorithm1_when_communication_dominates():
+    """No movement or in-pass cost and launches of their own costlier than a
+    tile pass: the time per gate falls with every link of the chain and never
+    favours the fallback, so the instructions are the oracle's Algorithm 1
+    (with its r / pinned variants), word for word."""
+    c = dict(tile=1.0, **{"in": (0.0, 0.0, 0.0)}, move=0.0, plain=(10.0,) * 4)
+    for g, n, m, r, pinned in [(paper_random_circuit(20, 600, 0.3, 4), 20, 16, 1, 0),
+                               (mixed_circuit(12, 150, 3), 12, 7, 1, 0),
+                               (layered_circuit(16, 12, seed=9), 16, 10, 4, 3),
+                               (config_circuit(2, n=20, layers=10), 20, 12, 16, 3)]:
+        ref, _ = O.pass_ref(g, n, m, r=r, pinned=pinned)
+        P = Q.Program(g, n, "c128", k_tile=m, max_swaps=r, pinned=pinned, costs=_pc(c))
+        ins = P.instructions()
+        P.close()
+        assert ins == ref
+
+
+@pytest.mark.parametrize("r,pinned,perm_exec,costs", [
+    (1, 0, "move", dict(tile=1.0, **{"in": (0.01, 0.02, 0.005)}, move=2.0, plain=(1.0, 1.0, 0.7, 1.1))),
+    (3, 0, "move", dict(tile=1.0, **{"in": (0.05, 0.08, 0.01)}, move=1.5, plain=(1.0, 1.0, 1.0, 1.0))),
+    (4, 1, "relabel", dict(tile=1.0, **{"in": (0.3, 0.5, 0.05)}, move=0.0, plain=(0.9, 0.9, 0.6, 1.0))),
+    (2, 0, "relabel", dict(tile=2.0, **{"in": (0.02, 0.4, 0.01)}, move=0.0, plain=(1.0, 1.0, 1.0, 1.0)))])
+@pytest.mark.parametrize("seed", range(4))
+def test_costed_pass_decisions_brute_force(r, pinned, perm_exec, costs, seed):
+    """Tiny circuits: every PermuteQubits / fallback gate of the costed pass is
+    the brute-force choice (see _expected_decision), every applied gate is
+    local and ready, and the compiled program computes the circuit."""
+    n, m = 6, 3 + seed % 2
+    g = mixed_circuit(n, 40, seed=3000 + seed) if seed % 2 else paper_random_circuit(n, 40, 0.4, seed=3000 + seed)
+    P = Q.Program(g, n, "c128", k_tile=m, max_swaps=r, pinned=pinned, perm_exec=perm_exec, costs=_pc(costs))
+    ins = P.instructions()
+    P.close()
+    preds = {v: set() for v in range(len(g))}
+    for h, v in O.dag_edges(g):
+        preds[v].add(h)
+    sigma, done = list(range(n)), set()
+    for op, arg in ins:
+        if op == "apply":
+            assert arg not in done and preds[arg] <= done and _is_local(g[arg], sigma, m)
+            done.add(arg)
+            continue
+        # a decision point: the sweep before it scheduled every local ready gate
+        assert not _closure_set(g, preds, done, sigma, m)
+        exp = _expected_decision(g, preds, done, sigma, m, r, pinned, costs)
+        if op == "perm":
+            assert exp == ("perm", tuple(arg))
+            sigma = list(arg)
+        else:
+            assert exp == ("global", arg)
+            done.add(arg)
+    assert done == set(range(len(g)))
+    v, sig = O.run_program(g, n, ins, x=7)
+    assert np.abs(O.to_logical(v, n, sig) - O.run(g, n, x=7)).max() < 1e-13
+
+
+def test_costed_pass_trades_permutations_for_launches_of_their_own():
+    """With moved placements (the paper's PermuteQubits) priced at two passes,
+    exchanges that make few gates local are replaced by gates run on their own
+    (the layered workload's shape: fewer PermuteQubits than Algorithm 1); with
+    relabelled placements a permutation costs nothing and the choices are
+    Algorithm 1's with maximal chains."""
+    n, m = 20, 12
+    g = config_circuit(2, n=n, layers=20)
+    c = dict(tile=1.0, **{"in": (0.02, 0.02, 0.005)}, move=2.0, plain=(1.0, 1.0, 1.0, 1.0))
+    P = Q.Program(g, n, "c128", k_tile=m, max_swaps=1, perm_exec="move", costs=_pc(c))
+    st = P.stats()
+    P.close()
+    ref = Q.Program(g, n, "c128", k_tile=m, max_swaps=1, perm_exec="move").stats()
+    assert st["n_global"] > ref["n_global"] and st["n_perm"] < ref["n_perm"]
+    c["move"] = 0.0
+    P = Q.Program(g, n, "c128", k_tile=m, max_swaps=16, pinned=3, costs=_pc(c))
+    ins = P.instructions()
+    P.close()
+    assert ins == Q.Program(g, n, "c128", k_tile=m, max_swaps=16, pinned=3).instructions()
+
+
+def test_costed_compile_rejects_bad_costs():
+    g = paper_random_circuit(8, 40, 0.3, seed=1)
+    for bad in (dict(tile=-1.0, **{"in": (0, 0, 0)}, move=0.0, plain=(1,) * 4),
+                dict(tile=1.0, **{"in": (0, float("nan"), 0)}, move=0.0, plain=(1,) * 4)):
+        with pytest.raises(Q.QsimError):
+            Q.Program(g, 8, "c128", k_tile=6, max_swaps=1, costs=_pc(bad))

@@ -37,3 +37,30 @@ def test_model_orders_clear_choices_like_the_device():
     assert pg < pp and mg < mp
     # the prediction is within a factor of two of the measurement
     assert 0.5 < pg / mg < 2.0
+
+
+@pytest.mark.parametrize("perm_exec,r,move", [("move", 1, 2.0), ("relabel", 4, 0.0)])
+def test_costed_pass_program_matches_oracle(perm_exec, r, move):
+    """A program whose PermuteQubits and gates run on their own were chosen by
+    predicted time (qs_compile_costed) computes the circuit: full vector
+    against the oracle."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2010_09746_amd import qsim as Q
+    from workloads import config_circuit
+
+    n = 16
+    g = config_circuit(2, n=n, layers=12)
+    costs = Q.make_pass_costs(1.0, (0.02, 0.03, 0.005), move, (1.0, 1.0, 0.8, 1.1))
+    P = Q.Program(g, n, "c128", form="pass", k_tile=10, max_swaps=r, pinned=0 if r == 1 else 3, perm_exec=perm_exec,
+                  costs=costs)
+    st = P.stats()
+    s = Q.State(n, "c128")
+    s.run_program(P)
+    v = s.to_numpy()
+    s.close()
+    P.close()
+    if perm_exec == "move":
+        assert st["n_global"] > 0
+    assert np.abs(v - O.run(g, n)).max() <= 1e-12
