@@ -107,7 +107,8 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *              multiply-adds per amplitude pair instead of 16.  The left
  *              factor F is kept pending on q and absorbed by q's next
  *              one-qubit gate: F = a I + b X when q's operations up to that
- *              gate are all CNOT targets (it commutes with them), else
+ *              gate are all CNOT targets (it commutes with them; complex128
+ *              only, since such factors amplify rounding errors), else
  *              M00 diag(1, z), applied before an operation that acts on q
  *              non-diagonally, with M00 in one scalar that the next gate
  *              applied whole takes.  The last gate of each qubit is applied

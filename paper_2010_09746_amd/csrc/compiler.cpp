@@ -529,6 +529,16 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 // inverse; for unitary M the best root reaches 5.8), its determinant leave
 // [1/16, 16], the scalar's magnitude [2^-8, 2^8], or |p|, |q| exceed 16,
 // so that complex64 states keep at least 2^-(2n+8) of their magnitude range.
+//
+// a I + b X pending factors are used for complex128 states only.  A diagonal
+// pending factor scales each stored amplitude, so rounding errors stay
+// relative to each amplitude; a I + b X mixes the two amplitudes of a pair,
+// and with many qubits holding one at once the stored state is their tensor
+// product's inverse applied to the true state: rounding errors come back
+// amplified (measured on the 22-qubit layered workload: maximum amplitude
+// error 2.6e-8 instead of 3.1e-9 in complex64, 1.5e-16 instead of 1.4e-17 in
+// complex128).  Complex64 keeps the diagonal form and its accuracy; complex128
+// stays near 1e-13 relative error.
 struct PhaseFrame {
     using cd = std::complex<double>;
     static constexpr double Z_LO = 0.25, Z_HI = 4.0, S_LO = 1.0 / 256.0, S_HI = 256.0, Q_MAX = 16.0;
@@ -551,7 +561,7 @@ struct PhaseFrame {
         return act == ACT_Z ? A_DIAG : act == ACT_X && gi.nq == 2 ? A_X : A_GEN;
     }
 
-    void init(const qs_gate *g, const std::vector<GateInfo> &gi, int64_t ng, int n)
+    void init(const qs_gate *g, const std::vector<GateInfo> &gi, int64_t ng, int n, bool allow_x)
     {
         type.assign(n, P_NONE);
         z.assign(n, cd(1.0, 0.0));
@@ -568,7 +578,7 @@ struct PhaseFrame {
             for (int k = 0; k < gi[v].nq; ++k) {
                 const int q = qs[k];
                 if (absorbing(g[v], gi[v])) {
-                    prefer_x[v] = state[q] == 1;
+                    prefer_x[v] = allow_x && state[q] == 1;
                     state[q] = 0;
                 } else {
                     state[q] = action(gi[v], q) == A_X && state[q] != 2 ? 1 : 2;
@@ -1219,7 +1229,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         // reduced one-qubit updates only where tile passes run them
         pf.on = tiled && (o.flags & QS_OPT_FULL_MATRICES) == 0;
         if (pf.on)
-            pf.init(g, gi, ng, n);
+            pf.init(g, gi, ng, n, dt == QS_C128);
         // Lower the instructions from i on.  A run of ApplyGate instructions is
         // a complete segment once an instruction of another kind follows it
         // (or, with final, at the end).

@@ -93,13 +93,14 @@ def test_pending_phase_settled_across_passes():
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_pending_factor_commuting_with_cnot_targets(dt):
-    """A qubit whose next operations are CNOT targets (or targets of
-    controlled gates in span{I, X}) keeps a I + b X pending: it commutes with
-    them, so no pending factor is applied on its own.  Exchange gates on the
-    targets absorb it; such a gate commutes with the CNOT target before it and
-    may be scheduled first, and the target then meets the exchange gate's own
-    diagonal factor (applied on its own).  Against the oracle and the
-    whole-matrix form."""
+    """complex128: a qubit whose next operations are CNOT targets (or targets
+    of controlled gates in span{I, X}) keeps a I + b X pending: it commutes
+    with them, so no pending factor is applied on its own.  Exchange gates on
+    the targets absorb it; such a gate commutes with the CNOT target before it
+    and may be scheduled first, and the target then meets the exchange gate's
+    own diagonal factor (applied on its own).  complex64 keeps diagonal
+    factors only (their phases are applied before the targets).  Against the
+    oracle and the whole-matrix form."""
     n = 14
     _say(f"a I + b X pending factors {dt}")
     X = np.array([[0, 1], [1, 0]], dtype=complex)
@@ -126,8 +127,11 @@ def test_pending_factor_commuting_with_cnot_targets(dt):
     g = circuit(True)
     n_u = int(sum(1 for k in g["kind"] if k == KIND_U))
     n_x = int(sum(1 for i in range(len(g)) if g["kind"][i] == KIND_U and g["u"][i][0] == 0 and g["u"][i][1] == 0))
-    assert counts[False]["phase"] == 0
-    assert counts[True]["phase"] <= n_x and counts[True]["shear"] > 0.8 * (n_u - n_x)
+    if dt == "c128":
+        assert counts[False]["phase"] == 0
+        assert counts[True]["phase"] <= n_x and counts[True]["shear"] > 0.8 * (n_u - n_x)
+    else:
+        assert counts[False]["phase"] > n_x and counts[True]["shear"] > 0.8 * (n_u - n_x)
     ref = O.run(g, n)
     a = _run(g, n, dt, **opts)
     b = _run(g, n, dt, full_matrices=True, **opts)
