@@ -50,6 +50,9 @@ def parse():
                     help="pinned positions for complex64 runs (precision and serving forms): 4 keeps the "
                          "lowest 16 amplitudes, one 128-byte line, in every tile")
     ap.add_argument("--reg-bits", type=int, default=0)
+    ap.add_argument("--costed", type=int, default=1,
+                    help="1: the pass decides each PermuteQubits by the measured cost model (calibrated once on "
+                         "this device before the warm-up, at --cal-n qubits); 0: Algorithm 1's step function")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain form (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = the OpenMP default)")
@@ -491,11 +494,16 @@ def costmodel_form(a):
     chosen = pick[0]["measured_ms"]
     in_pass = []
     n_rf = a.n - 2
-    cases = [("layered", gates, a.n, dict(best)),
-             ("layered, moved placements, r=1", gates, a.n,
-              dict(k_tile=a.k, max_swaps=1, pinned=0, perm_exec="move", reg_bits=0)),
-             ("random family p=1, moved placements, r=1", paper_random_circuit(n_rf, 30 * n_rf, 1.0, 20100946 + 8),
-              n_rf, dict(k_tile=a.k, max_swaps=1, pinned=0, perm_exec="move", reg_bits=0))]
+    rf = {p: paper_random_circuit(n_rf, 30 * n_rf, p, 20100946 + 8) for p in (0.3, 1.0)}
+    cases = [("layered", gates, a.n, dict(best))]
+    for p, g in rf.items():
+        # the best global options for this circuit (relabelled placements)
+        b, _ = cm.choose(g, n_rf, ks=(11, 12, 13), rs=(8, 16), reg_bits=(4,))
+        cases.append((f"random family p={p}", g, n_rf, dict(b)))
+    cases += [("layered, moved placements, r=1", gates, a.n,
+               dict(k_tile=a.k, max_swaps=1, pinned=0, perm_exec="move", reg_bits=0)),
+              ("random family p=1, moved placements, r=1", rf[1.0], n_rf,
+               dict(k_tile=a.k, max_swaps=1, pinned=0, perm_exec="move", reg_bits=0))]
     for name, g, n, opts in cases:
         row = {"workload": name, "n": n, "opts": opts}
         costs = cm.pass_costs(n, opts["k_tile"], opts["reg_bits"], opts["perm_exec"])
@@ -504,7 +512,7 @@ def costmodel_form(a):
             P = Q.Program(g, n, a.dtype, form="pass", costs=c, **opts)
             prog_stats = {k: P.stats()[k] for k in ("n_perm", "n_global", "n_tile_passes")}
             P.close()
-            row[tag] = dict(predicted_ms=ms, measured_ms=costmodel.measure_ms(g, n, a.dtype, opts, reps=1, costs=c),
+            row[tag] = dict(predicted_ms=ms, measured_ms=costmodel.measure_ms(g, n, a.dtype, opts, reps=3, costs=c),
                             **prog_stats)
         row["pass_costs"] = costs
         in_pass.append(row)
@@ -562,10 +570,20 @@ def main():
 
     pass_opts = dict(form="pass", k_tile=a.k, max_swaps=a.r, perm_exec=a.perm_exec, pinned=a.pinned,
                      reg_bits=a.reg_bits)
+    costs, cost_info = None, None
+    if a.costed:
+        from paper_2010_09746_amd import costmodel
+
+        t0 = time.perf_counter()
+        cm = costmodel.CostModel(dt, n_cal=a.cal_n, perm_exec=a.perm_exec, pinned=a.pinned)
+        pc = cm.pass_costs(n, a.k, a.reg_bits, a.perm_exec)
+        costs = cm.as_struct(pc)
+        cost_info = dict(calibration_seconds=time.perf_counter() - t0, n_cal=a.cal_n, pass_costs_ms=pc)
+        torch.cuda.empty_cache()
 
     def step(opts):
         st.set_basis(0)
-        st.run(gates, **opts)
+        st.run(gates, costs=costs if opts.get("form") == "pass" else None, **opts)
         z = st.expect_z()
         amp = st.amplitudes(samples)
         return z, amp
@@ -585,7 +603,7 @@ def main():
         prof = Q.qs_profile_read()
         return el / steps, prof, out
 
-    prog = Q.Program(gates, n, dt, **pass_opts)
+    prog = Q.Program(gates, n, dt, costs=costs, **pass_opts)
     pstats = prog.stats()
     prog.close()
 
@@ -680,11 +698,13 @@ def main():
             "workload": f"random circuit, n={n} {dt}, {a.layers} layers of Haar U(2) on every qubit + CNOT on a "
                         f"random perfect matching (CZ every third layer), {len(gates)} gates; read-out <Z_q> all q "
                         f"+ {len(samples)} sampled amplitudes",
-            "form": f"permutation pass k={a.k} r={a.r} pinned={a.pinned} perm_exec={a.perm_exec}",
+            "form": f"permutation pass k={a.k} r={a.r} pinned={a.pinned} perm_exec={a.perm_exec}"
+                    + (" (PermuteQubits chosen by the measured cost model)" if a.costed else ""),
             "parallelism": "1 GPU",
         },
-        "pass_stats": {k: pstats[k] for k in ("n_perm", "n_swaps", "n_tile_passes", "n_move_passes", "n_remaps",
-                                              "compile_ms")},
+        "pass_stats": {k: pstats[k] for k in ("n_perm", "n_global", "n_swaps", "n_tile_passes", "n_move_passes",
+                                              "n_remaps", "compile_ms")},
+        "cost_model": cost_info,
         "kernels": {k: dict(launches=v["launches"], avg_ms=v["avg_ms"],
                             achieved_gbs=v["bytes"] / max(v["total_ms"], 1e-9) / 1e6)
                     for k, v in prof_pass.items()},

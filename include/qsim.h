@@ -281,6 +281,14 @@ qs_status qs_run_program(qs_state *s, const qs_program *p);
 qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates,
                          const qs_run_opts *opts);
 
+/* qs_run_circuit with the pass deciding by predicted time, as
+ * qs_compile_costed (costs: host, read during the call).  The placement
+ * choices and the launches they lead to are those of qs_compile_costed;
+ * each segment's tile pass is enqueued as soon as the permutation after it is
+ * chosen. */
+qs_status qs_run_circuit_costed(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
+                                const qs_pass_costs *costs);
+
 /* ---- allocation-free run -------------------------------------------------- */
 
 /* Tile operations a program run by qs_run_program_noalloc may hold. */

@@ -622,6 +622,14 @@ qs_status qs_permute_qubits(qs_state *s, const int *sigma_new)
 }
 
 namespace {
+void check_costs(const qs_pass_costs &c)
+{
+    const double v[] = {c.tile_pass, c.in_pass[0], c.in_pass[1], c.in_pass[2], c.move,
+                        c.plain[0], c.plain[1], c.plain[2], c.plain[3]};
+    for (double x : v)
+        need(std::isfinite(x) && x >= 0.0, "pass costs must be finite and non-negative");
+}
+
 qs_status compile_entry(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
                         const qs_run_opts *opts, const qs_pass_costs *costs, qs_program **out)
 {
@@ -639,12 +647,8 @@ qs_status compile_entry(const qs_gate *gates, int64_t n_gates, int n, qs_dtype d
         qs_run_opts o = opts ? *opts : default_opts();
         if (o.form == QS_FORM_PASS)
             need(o.k_tile >= 1, "k_tile must be >= 1");
-        if (costs) {
-            const double v[] = {costs->tile_pass, costs->in_pass[0], costs->in_pass[1], costs->in_pass[2],
-                                costs->move, costs->plain[0], costs->plain[1], costs->plain[2], costs->plain[3]};
-            for (double x : v)
-                need(std::isfinite(x) && x >= 0.0, "pass costs must be finite and non-negative");
-        }
+        if (costs)
+            check_costs(*costs);
         auto *p = new qs_program();
         try {
             compile_program(gates, n_gates, n, dt, sigma0, o, p->p, {}, costs);
@@ -666,9 +670,9 @@ qs_status qs_compile(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, 
 qs_status qs_compile_costed(const qs_gate *gates, int64_t n_gates, int n, qs_dtype dt, const int *sigma0,
                             const qs_run_opts *opts, const qs_pass_costs *costs, qs_program **out)
 {
-    return guard([&] { need(costs != nullptr, "costs is NULL"); }) == QS_OK
-               ? compile_entry(gates, n_gates, n, dt, sigma0, opts, costs, out)
-               : QS_ERR_ARG;
+    if (!costs)
+        return guard([&] { need(false, "costs is NULL"); });
+    return compile_entry(gates, n_gates, n, dt, sigma0, opts, costs, out);
 }
 
 qs_status qs_program_destroy(qs_program *p)
@@ -801,12 +805,16 @@ qs_status qs_run_program(qs_state *s, const qs_program *p)
 // Compile and run.  In the pass form the launches of each segment are
 // enqueued as soon as the pass has fixed it, so the device works on the first
 // segments while the host is still choosing later permutations.
-qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts)
+namespace {
+qs_status run_circuit_entry(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
+                            const qs_pass_costs *costs)
 {
     return guard([&] {
         need(s != nullptr, "state is NULL");
         need(n_gates >= 0 && (n_gates == 0 || gates != nullptr), "bad arguments");
         const qs_run_opts o = opts ? *opts : default_opts();
+        if (costs)
+            check_costs(*costs);
         Program p;
         // the plain form's program table, freed on every way out (after the
         // stream has been synchronised)
@@ -818,9 +826,10 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, con
                     (void)hipFree(p.d_ops);
             }
         } free_ops{p};
-        // every gate gives at most one operation and one re-layout, plus one
-        // re-layout per segment
-        const size_t bound = 3 * (size_t)n_gates + 16;
+        // every gate gives at most its operation, two pending factors applied
+        // before it and one re-layout; every segment (at most one per gate)
+        // one more re-layout and two lane swaps
+        const size_t bound = 7 * (size_t)n_gates + 16;
         if (o.form == QS_FORM_PASS)
             ensure_op_buffers(s, bound);
         size_t launched = 0, uploaded = 0;
@@ -840,7 +849,7 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, con
         };
         if (o.form == QS_FORM_PASS) {
             try {
-                compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p, progress);
+                compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p, progress, costs);
             } catch (...) {
                 // launches already enqueued read the op tables: let them
                 // finish before the error is reported (the state then holds a
@@ -861,6 +870,20 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, con
         // the tables (and the staging the copies read) are reused next call
         hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     });
+}
+}  // namespace
+
+qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts)
+{
+    return run_circuit_entry(s, gates, n_gates, opts, nullptr);
+}
+
+qs_status qs_run_circuit_costed(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
+                                const qs_pass_costs *costs)
+{
+    if (!costs)
+        return guard([&] { need(false, "costs is NULL"); });
+    return run_circuit_entry(s, gates, n_gates, opts, costs);
 }
 
 qs_status qs_synchronize(qs_state *s)

@@ -47,7 +47,7 @@ EXPORTS = [
     "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_plan",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
     "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
-    "qs_run_program_noalloc", "qs_compile_costed",
+    "qs_run_program_noalloc", "qs_compile_costed", "qs_run_circuit_costed",
 ]
 
 
@@ -150,6 +150,8 @@ def load() -> ctypes.CDLL:
     L.qs_run_program.argtypes = [_vp, _vp]
     L.qs_run_program_noalloc.argtypes = [_vp, _vp]
     L.qs_run_circuit.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.POINTER(qs_run_opts)]
+    L.qs_run_circuit_costed.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.POINTER(qs_run_opts),
+                                        ctypes.POINTER(qs_pass_costs)]
     L.qs_read_amplitudes.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
     L.qs_read_state.argtypes = [_vp, _vp]
     L.qs_expect_z.argtypes = [_vp, _vp]
@@ -356,6 +358,12 @@ def qs_run_program_noalloc(h: int, prog: int) -> None:
 def qs_run_circuit(h: int, gates, opts: qs_run_opts | None = None) -> None:
     g = as_gates(gates)
     _chk(load().qs_run_circuit(h, g.ctypes.data, len(g), ctypes.byref(opts) if opts is not None else None))
+
+
+def qs_run_circuit_costed(h: int, gates, opts: qs_run_opts | None = None, costs: qs_pass_costs | None = None) -> None:
+    g = as_gates(gates)
+    _chk(load().qs_run_circuit_costed(h, g.ctypes.data, len(g), ctypes.byref(opts) if opts is not None else None,
+                                      ctypes.byref(costs) if costs is not None else None))
 
 
 def qs_read_amplitudes(h: int, idx) -> np.ndarray:
@@ -590,8 +598,11 @@ class State:
         qs_permute_qubits(self.h, sigma_new)
         return self
 
-    def run(self, gates, **opts) -> "State":
-        qs_run_circuit(self.h, gates, make_opts(**opts))
+    def run(self, gates, costs: qs_pass_costs | None = None, **opts) -> "State":
+        if costs is None:
+            qs_run_circuit(self.h, gates, make_opts(**opts))
+        else:
+            qs_run_circuit_costed(self.h, gates, make_opts(**opts), costs)
         return self
 
     def run_program(self, prog: "Program", noalloc: bool = False) -> "State":

@@ -63,4 +63,11 @@ def test_costed_pass_program_matches_oracle(perm_exec, r, move):
     P.close()
     if perm_exec == "move":
         assert st["n_global"] > 0
-    assert np.abs(v - O.run(g, n)).max() <= 1e-12
+    ref = O.run(g, n)
+    assert np.abs(v - ref).max() <= 1e-12
+    # the same choices when the pass and the launches advance together
+    s = Q.State(n, "c128")
+    s.run(g, costs=costs, form="pass", k_tile=10, max_swaps=r, pinned=0 if r == 1 else 3, perm_exec=perm_exec)
+    w = s.to_numpy()
+    s.close()
+    assert np.abs(w - ref).max() <= 1e-12
