@@ -270,38 +270,61 @@ def test_empty_circuit_and_identity_permutation():
 # pass form agrees with the independent plain kernels on sampled amplitudes and
 # on every <Z_q>, and the norm stays 1.
 
+_COSTS = {}
+
+
+def _bench_costs(dt, n):
+    """The pass costs bench.py's headline uses: the measured cost model,
+    calibrated on this device at 27 qubits, for k = 12 and n qubits."""
+    from paper_2010_09746_amd import costmodel
+
+    if dt not in _COSTS:
+        _COSTS[dt] = costmodel.CostModel(dt, n_cal=27, perm_exec="relabel", pinned=3)
+    cm = _COSTS[dt]
+    return cm.as_struct(cm.pass_costs(n, 12, 0, "relabel"))
+
+
 def test_config2_full_size_pass_vs_plain():
     n = 30
     # the launch configuration bench.py times (k = 12, r = 16, relabel, 3
-    # pinned, the default register shape: 16 amplitudes per thread)
-    _say("config-2 full size: pass (k=12, r=16, relabel) vs plain")
+    # pinned, the default register shape: 16 amplitudes per thread; the pass
+    # deciding by the calibrated cost model), and the same with Algorithm 1's
+    # step function
+    _say("config-2 full size: pass (k=12, r=16, relabel; costed and step function) vs plain")
     g = config_circuit(2)
     idx = config_samples(2)
-    a = Q.State(n, "c128")
-    a.run(g, form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=3)
-    za, amp_a, na = a.expect_z(), a.amplitudes(idx), a.norm()
-    a.close()
-    del a
-    torch.cuda.empty_cache()
+    opts = dict(form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=3)
+    res = []
+    for costs in (_bench_costs("c128", n), None):
+        a = Q.State(n, "c128")
+        a.run(g, costs=costs, **opts)
+        res.append((a.expect_z(), a.amplitudes(idx), a.norm()))
+        a.close()
+        del a
+        torch.cuda.empty_cache()
     b = Q.State(n, "c128")
     b.run(g, form="plain")
     zb, amp_b = b.expect_z(), b.amplitudes(idx)
-    assert abs(na - 1) <= 1e-12
-    assert np.abs(amp_a - amp_b).max() <= 1e-12
-    assert np.abs(za - zb).max() <= 1e-12
+    for za, amp_a, na in res:
+        assert abs(na - 1) <= 1e-12
+        assert np.abs(amp_a - amp_b).max() <= 1e-12
+        assert np.abs(za - zb).max() <= 1e-12
 
 
-@pytest.mark.parametrize("dt,n,pinned", [("c128", 24, 3), ("c64", 22, 4)])
-def test_bench_launch_configuration_vs_oracle(dt, n, pinned):
+@pytest.mark.parametrize("dt,n,pinned,costed", [("c128", 24, 3, True), ("c128", 24, 3, False), ("c64", 22, 4, False)])
+def test_bench_launch_configuration_vs_oracle(dt, n, pinned, costed):
     """The launch configuration bench.py times (k = 12, r = 16, relabelled
     placements, the default register shape: 16 amplitudes per thread; 3
-    pinned positions for complex128, 4 for complex64) on the benchmark's
-    circuit family at a size where 10-12 qubits lie outside the tile, so that
-    PermuteQubits bundles of many exchanges form; full vector against the
-    oracle."""
-    _say(f"bench configuration vs oracle {dt} n={n} pinned={pinned}")
+    pinned positions for complex128, 4 for complex64; complex128 with the
+    pass deciding by the calibrated cost model as in the headline) on the
+    benchmark's circuit family at a size where 10-12 qubits lie outside the
+    tile, so that PermuteQubits bundles of many exchanges form; full vector
+    against the oracle."""
+    _say(f"bench configuration vs oracle {dt} n={n} pinned={pinned} costed={costed}")
     g = config_circuit(2, n=n)
     opts = dict(form="pass", k_tile=12, max_swaps=16, perm_exec="relabel", pinned=pinned)
+    if costed:
+        opts["costs"] = _bench_costs(dt, n)
     P = Q.Program(g, n, dt, **opts)
     ps = P.stats()
     P.close()
