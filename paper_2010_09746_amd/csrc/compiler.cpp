@@ -542,7 +542,7 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 struct PhaseFrame {
     using cd = std::complex<double>;
     static constexpr double Z_LO = 0.25, Z_HI = 4.0, S_LO = 1.0 / 256.0, S_HI = 256.0, Q_MAX = 16.0;
-    static constexpr double DET_LO = 1.0 / 16.0, DET_HI = 16.0, K_X = 8.0;
+    static constexpr double DET_LO = 1.0 / 16.0, DET_HI = 16.0, K_X = 8.0, RESIDUAL = 1e-13;
     enum : int8_t { P_NONE = 0, P_DIAG = 1, P_XT = 2 };
     enum Action { A_DIAG, A_X, A_GEN };
     bool on = false;
@@ -647,6 +647,17 @@ struct PhaseFrame {
                     continue;
                 const double kappa = std::max(e1 / e2, e2 / e1), ad = std::abs(det);
                 if (kappa > K_X || ad < DET_LO || ad > DET_HI || std::abs(p) > Q_MAX || std::abs(q) > Q_MAX)
+                    continue;
+                // the root can lose digits to cancellation: keep the candidate
+                // only if (a I + b X) L(q) U(p) gives back the matrix
+                const cd back[4] = {aa + bb * q, aa * p + bb * (1.0 + q * p), bb + aa * q, bb * p + aa * (1.0 + q * p)};
+                const cd mm[4] = {m00, m01, m10, m11};
+                double err = 0.0, scale = 0.0;
+                for (int i = 0; i < 4; ++i) {
+                    err = std::max(err, std::abs(back[i] - mm[i]));
+                    scale = std::max(scale, std::abs(mm[i]));
+                }
+                if (err > RESIDUAL * scale)
                     continue;
                 if (!found || kappa < best) {
                     found = true;
