@@ -125,7 +125,11 @@ def traffic_from_counters(a):
         rows = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == ctr]
-        tile = [float(r["Counter_Value"]) for r in rows if "k_tile<double, 8, 4" in r["Kernel_Name"]]
+        # the workload's own passes: the largest grid (the cost model's
+        # calibration passes run on a smaller state first)
+        tile_rows = [r for r in rows if "k_tile<double, 8, 4" in r["Kernel_Name"]]
+        grid = max((int(r["Grid_Size"]) for r in tile_rows), default=0)
+        tile = [float(r["Counter_Value"]) for r in tile_rows if int(r["Grid_Size"]) == grid]
         copy = sorted(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])[-3:]
         if not tile or len(copy) < 3:
             raise SystemExit(f"{d}: no tile-pass or copy dispatches for {ctr}")
@@ -456,7 +460,8 @@ def random_family(a):
 
 def ablation(a):
     """The 30-qubit workload under Algorithm 1 as printed (r = 1), the bundled
-    pass over tile sizes 10..14 and fusion without the pass (r = 0)."""
+    pass over tile sizes 10..14, fusion without the pass (r = 0) and gates on
+    the lowest thread bits through lane exchanges."""
     from paper_2010_09746_amd import studies
 
     r = studies.ablation_study(n=a.n, dtype=a.dtype, layers=a.layers, r=a.r, k_ref=a.k)
@@ -464,7 +469,7 @@ def ablation(a):
     ref = next(x for x in r["rows"] if x["variant"] == "fusion without pass")
     _study_line("pass speedup over fusion without the pass", ref["ms"] / best["ms"], "x", best["ms"],
                 {"workload": f"layered circuit n={a.n} {a.dtype}, {r['gates']} gates: r=0 and r=1 at k={a.k}, "
-                             f"r={a.r} at k=10..14; device time of one run each"}, r)
+                             f"r={a.r} at k=10..14, lane gates at k={a.k}; device time of one run each"}, r)
 
 
 def costmodel_form(a):

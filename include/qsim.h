@@ -113,8 +113,18 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *              non-diagonally, with M00 in one scalar that the next gate
  *              applied whole takes.  The last gate of each qubit is applied
  *              whole.  Same result up to rounding.
+ *              QS_OPT_LANE_GATES / QS_OPT_LANE_GATES_WIDE: an uncontrolled
+ *              one-qubit gate whose target is on thread-id bit 0 or 1 (bits
+ *              0..3 with _WIDE) of the tile layout in force may run there,
+ *              applied whole through lane exchanges (DPP moves) instead of
+ *              after a register re-layout through LDS: only when every ready
+ *              gate that waits for a re-layout can (the re-layout is put
+ *              off), or, with QS_OPT_LANE_EAGER as well, whenever it is
+ *              ready.  Off by default: on the 30-qubit layered workload they
+ *              cost more than the re-layouts they save.  Same result up to
+ *              rounding.
  */
-enum { QS_OPT_FULL_MATRICES = 1 };
+enum { QS_OPT_FULL_MATRICES = 1, QS_OPT_LANE_GATES = 2, QS_OPT_LANE_GATES_WIDE = 4, QS_OPT_LANE_EAGER = 8 };
 typedef struct {
     int32_t form;
     int32_t k_tile;
@@ -239,6 +249,9 @@ qs_status qs_program_get_stats(const qs_program *p, qs_program_stats *out);
  *   QS_OPC_SHEAR       one-qubit updates as two shears (see flags)
  *   QS_OPC_PHASE       pending diagonals applied on their own (see flags)
  *   QS_OPC_LSWAP       exchanges of a register bit with a lane bit in registers
+ *   QS_OPC_LANE        one-qubit gates through lane exchanges (see flags)
+ *   QS_OPC_REMAP_WAVE  re-layouts that keep the tile bits on the wavefront
+ *                      bits of the thread id (no barrier; also in QS_OPC_REMAP)
  * Writes min(cap, QS_OPC_COUNT) entries. */
 enum {
     QS_OPC_TILE_PASS = 0,
@@ -259,7 +272,9 @@ enum {
     QS_OPC_SHEAR = 15,     /* one-qubit update as two shears */
     QS_OPC_PHASE = 16,     /* pending diagonal applied on its own */
     QS_OPC_LSWAP = 17,     /* register slot bit <-> lane bit exchange (no LDS) */
-    QS_OPC_COUNT = 18
+    QS_OPC_LANE = 18,      /* one-qubit 2x2 on a lane bit through lane exchanges */
+    QS_OPC_REMAP_WAVE = 19, /* re-layouts (counted in QS_OPC_REMAP too) local to each wavefront: no barrier */
+    QS_OPC_COUNT = 20
 };
 qs_status qs_program_op_counts(const qs_program *p, double *out, int cap);
 

@@ -713,6 +713,7 @@ qs_status qs_program_op_counts(const qs_program *p, double *out, int cap)
                     const TileOp &o = P.ops[L.op_begin + i];
                     if (o.kind == OP_REMAP) {
                         c[QS_OPC_REMAP] += 1;
+                        c[QS_OPC_REMAP_WAVE] += (o.aux & REMAP_WAVE_LOCAL) ? 1 : 0;
                         continue;
                     }
                     if (o.kind == OP_SHEAR2) {
@@ -721,6 +722,10 @@ qs_status qs_program_op_counts(const qs_program *p, double *out, int cap)
                     }
                     if (o.kind == OP_LSWAP) {
                         c[QS_OPC_LSWAP] += 1;
+                        continue;
+                    }
+                    if (o.kind == OP_LANE) {
+                        c[QS_OPC_LANE] += 1;
                         continue;
                     }
                     const double w = std::ldexp(1.0, -__builtin_popcountll(o.hmask));

@@ -753,8 +753,13 @@ struct PhaseFrame {
 // may be reordered only along the commutation DAG restricted to the segment.
 constexpr int LOOKAHEAD_TARGETS = 8;
 
+// With lane_bits > 0, an uncontrolled one-qubit gate whose target sits on one
+// of the lowest lane_bits thread-id bits of the current layout may run there
+// through lane exchanges (OP_LANE, applied whole) instead of waiting for a
+// re-layout: when every ready gate that needs a register slot is such a gate
+// (so the re-layout is put off), or, with lane_eager, as soon as it is ready.
 int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::vector<GateInfo> &gi,
-                     int k, int log_r, std::vector<TileOp> &ops, PhaseFrame &pf)
+                     int k, int log_r, std::vector<TileOp> &ops, PhaseFrame &pf, int lane_bits, bool lane_eager)
 {
     const int cnt = (int)lg.size();
     // in-segment predecessors
@@ -773,6 +778,7 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
     const size_t seg_begin = ops.size();
     const int R = log_r;
     int regs[8];
+    int thread_of[16];  // tile bit -> thread-id bit of the current layout (-1: a register slot)
     bool have = false;
     auto in_regs = [&](int tb) {
         if (!have)
@@ -789,6 +795,31 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
         return true;
     };
     auto needs_reg = [&](int v) { return lg[v].kind == OP_U || lg[v].kind == OP_X; };
+    // thread-id bit of gate v's target when it may run as OP_LANE, else -1
+    auto lane_of = [&](int v) {
+        const LGate &L = lg[v];
+        if (lane_bits <= 0 || !have || L.kind != OP_U || L.cmask != 0 || L.hmask != 0 ||
+            g[L.src].kind != QS_GATE_U || in_regs(L.tb) >= 0)
+            return -1;
+        const int i = thread_of[L.tb];
+        return i >= 0 && i < lane_bits ? i : -1;
+    };
+    auto emit_lane = [&](int v, int i) {
+        TileOp op{};
+        op.kind = OP_LANE;
+        op.tlane = (uint32_t)i;
+        std::memcpy(op.m, lg[v].m, sizeof op.m);
+        if (pf.on) {
+            // applied whole: q's pending factor and the scalar are taken
+            const qs_gate &src = g[lg[v].src];
+            int32_t kind = 0;
+            bool flip = false;
+            pf.one_qubit(-1, src.q0, src.u, &kind, op.m, &flip);
+        }
+        ops.push_back(op);
+        emitted[v] = 1;
+        --left;
+    };
     while (left > 0) {
         bool progress = true;
         while (progress) {
@@ -799,6 +830,14 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
                 int slot = -1;
                 if (!have)
                     continue;   // ops act on register data: a layout must exist
+                if (lane_eager) {
+                    const int i = lane_of(v);
+                    if (i >= 0) {
+                        emit_lane(v, i);
+                        progress = true;
+                        continue;
+                    }
+                }
                 if (needs_reg(v)) {
                     slot = in_regs(lg[v].tb);
                     if (slot < 0)
@@ -881,6 +920,22 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
         }
         if (left == 0)
             break;
+        if (lane_bits > 0 && have) {
+            // every blocked ready gate can run on its lane bit: no re-layout yet
+            std::vector<std::pair<int, int>> lane;
+            bool all = true;
+            for (int v = 0; v < cnt && all; ++v)
+                if (!emitted[v] && ready(v) && needs_reg(v)) {
+                    const int i = lane_of(v);
+                    all = i >= 0;
+                    lane.emplace_back(v, i);
+                }
+            if (all && !lane.empty()) {
+                for (const auto &vi : lane)
+                    emit_lane(vi.first, vi.second);
+                continue;
+            }
+        }
         // re-layout: targets of ready gates first, then of later gates
         std::vector<int> want;
         auto add = [&](int tb) {
@@ -959,6 +1014,7 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
             bool reg = false;
             for (int s = 0; s < R; ++s)
                 reg |= regs[s] == b;
+            thread_of[b] = reg ? -1 : i;
             if (!reg)
                 lanes |= (uint64_t)b << (4 * i++);
         }
@@ -968,6 +1024,75 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
         ++remaps;
     }
     return remaps;
+}
+
+// Wavefront-local re-layouts.  The thread-id bits above the lane bits (6 and
+// up) number the wavefronts of a workgroup.  A re-layout that leaves the same
+// tile bits on them moves amplitudes only between the lanes and registers of
+// each wavefront: every wavefront reads back from LDS only the slots it wrote
+// itself, and a wavefront's LDS instructions run in order, so the re-layout
+// needs no barrier (OP_REMAP with aux bit REMAP_WAVE_LOCAL).  The register
+// sets of the segment's re-layouts are fixed by the scheduler; this picks the
+// tile bits of the wavefront bits: at each re-layout that must move them
+// (its register set takes one of them, or the first of the pass), the tile
+// bits outside its register set and outside the lowest `low` bits (which stay
+// on lane bits for whole 128-byte lines at load and store) whose next use in
+// a register set comes last; the other thread bits take the remaining tile
+// bits in ascending order.
+void assign_wave_bits(std::vector<TileOp> &ops, size_t begin, int k, int log_r, int log_nt, int low)
+{
+    const int nw = log_nt - 6;
+    if (nw <= 0)
+        return;
+    std::vector<size_t> rl;
+    for (size_t i = begin; i < ops.size(); ++i)
+        if (ops[i].kind == OP_REMAP)
+            rl.push_back(i);
+    std::vector<uint32_t> sets(rl.size(), 0u);
+    for (size_t j = 0; j < rl.size(); ++j)
+        for (int s = 0; s < log_r; ++s)
+            sets[j] |= 1u << ((ops[rl[j]].rmask >> (4 * s)) & 15u);
+    uint32_t W = 0;
+    for (size_t j = 0; j < rl.size(); ++j) {
+        TileOp &op = ops[rl[j]];
+        const bool keep = j > 0 && W != 0 && (sets[j] & W) == 0;
+        if (!keep) {
+            // candidates by next use (never: past the end), higher bits first on ties
+            std::vector<std::pair<size_t, int>> cand;
+            for (int b = k - 1; b >= low; --b) {
+                if ((sets[j] >> b) & 1u)
+                    continue;
+                size_t next = rl.size();
+                for (size_t t = j + 1; t < rl.size(); ++t)
+                    if ((sets[t] >> b) & 1u) {
+                        next = t;
+                        break;
+                    }
+                cand.emplace_back(next, b);
+            }
+            if ((int)cand.size() < nw) {
+                W = 0;  // keep the ascending map
+                continue;
+            }
+            std::stable_sort(cand.begin(), cand.end(),
+                             [](const std::pair<size_t, int> &a, const std::pair<size_t, int> &b) {
+                                 return a.first > b.first;
+                             });
+            W = 0;
+            for (int i = 0; i < nw; ++i)
+                W |= 1u << cand[i].second;
+        }
+        uint64_t lanes = 0;
+        int i = 0;
+        for (int b = 0; b < k; ++b)
+            if (!((sets[j] >> b) & 1u) && !((W >> b) & 1u))
+                lanes |= (uint64_t)b << (4 * i++);
+        for (int b = 0; b < k; ++b)
+            if ((W >> b) & 1u)
+                lanes |= (uint64_t)b << (4 * i++);
+        op.hbit = lanes;
+        op.aux = keep ? REMAP_WAVE_LOCAL : 0u;
+    }
 }
 
 // Tile bits that must be thread bits for each load or store instruction to
@@ -1228,6 +1353,8 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
             fail(QS_ERR_ARG, "pinned must be in [0, k_tile]");
         if (o.perm_exec != QS_PERM_MOVE && o.perm_exec != QS_PERM_RELABEL)
             fail(QS_ERR_ARG, "unknown perm_exec");
+        if (o.flags & ~(QS_OPT_FULL_MATRICES | QS_OPT_LANE_GATES | QS_OPT_LANE_GATES_WIDE | QS_OPT_LANE_EAGER))
+            fail(QS_ERR_ARG, "unknown flags");
         // tile passes need 7 <= k and a tile that fits in one CU's LDS; a larger
         // local set (e.g. a pass planned for several devices) runs its
         // segments gate by gate
@@ -1241,6 +1368,8 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         pf.on = tiled && (o.flags & QS_OPT_FULL_MATRICES) == 0;
         if (pf.on)
             pf.init(g, gi, ng, n, dt == QS_C128);
+        const int lane_bits = (o.flags & QS_OPT_LANE_GATES_WIDE) ? 4 : (o.flags & QS_OPT_LANE_GATES) ? 2 : 0;
+        const bool lane_eager = (o.flags & QS_OPT_LANE_EAGER) != 0;
         // Lower the instructions from i on.  A run of ApplyGate instructions is
         // a complete segment once an instruction of another kind follows it
         // (or, with final, at the end).
@@ -1305,7 +1434,10 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                     L.log_nt = log_nt;
                     L.pos = pos;
                     L.op_begin = (int)p.ops.size();
-                    p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops, pf);
+                    p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops, pf, lane_bits, lane_eager);
+                    // lane gates name thread bits of the ascending map
+                    if (lane_bits == 0)
+                        assign_wave_bits(p.ops, (size_t)L.op_begin, k, log_r, log_nt, direct_low_bits(dt));
                     L.op_count = (int)p.ops.size() - L.op_begin;
                     append_store_lane_swaps(L, p.ops, dt);
                     set_direct_io(L, p.ops, dt);

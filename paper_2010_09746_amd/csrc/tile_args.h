@@ -16,7 +16,9 @@ enum TileOpKind : int32_t {
     OP_NEG = 3,    // negate where every control bit is 1
     OP_REMAP = 4,  // move amplitudes through LDS to a new register layout: rmask and hbit
                    // give its register and thread tile bits, the first words of m the
-                   // LDS slot (lds_swizzle) of each register slot bit (word s: slot bit s)
+                   // LDS slot (lds_swizzle) of each register slot bit (word s: slot bit s);
+                   // aux & REMAP_WAVE_LOCAL: the tile bits on the wavefront-index bits of
+                   // the thread id stay, so no barrier is needed
     OP_SHEAR = 5,  // on the pair (x, y) of register slot `slot`: x += p y, then y += q x, with
                    // p = (m[0], m[1]) and q = (m[2], m[3]); tlane != 0: exchange x and y
                    // first (a relabelling); no controls
@@ -29,7 +31,11 @@ enum TileOpKind : int32_t {
                    // wavefront, in registers: the tile bit lmask (on the lane bit) moves into
                    // the slot, the tile bit rmask (on the slot) onto the lane bit; the first
                    // word of m is the slot's new LDS slot (lds_swizzle of lmask)
+    OP_LANE = 9,   // dense 2x2 (m[0..7]) on thread-id bit tlane (< 4) of the layout, through
+                   // lane exchanges (DPP) instead of a re-layout; no controls
 };
+
+constexpr uint32_t REMAP_WAVE_LOCAL = 1u;
 
 // One operation of a fused tile pass (104 bytes, every field at least 32 bits
 // wide and naturally aligned so that the kernel reads it with scalar loads).  Its controls are split by
@@ -46,7 +52,7 @@ struct TileOp {
     uint32_t rmask;    // OP_REMAP: register tile bits, 4 bits each (slot s at bits 4s..4s+3)
     uint32_t lmask;
     uint32_t tlane;
-    uint32_t aux;      // OP_SHEAR2: the second shear's slot and exchange flag
+    uint32_t aux;      // OP_SHEAR2: the second shear's slot and exchange flag; OP_REMAP: flags
     uint64_t hmask;
     uint64_t hbit;     // OP_DIAG target outside the tile; OP_REMAP: the tile bit of each
                        // thread-id bit, 4 bits each (thread bit i at bits 4i..4i+3)

@@ -286,6 +286,62 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
         }
     }
 
+    // One-qubit 2x2 on thread bit B < 4 (a lane bit of the wavefront), every
+    // register amplitude: each lane reads the amplitude of lane tid ^ 2^B by
+    // DPP moves within rows of 16 lanes (one quad permutation for bits 0 and
+    // 1; a half-row mirror, XOR 7, and the quad permutation XOR 3 for bit 2;
+    // a row mirror, XOR 15, and a half-row mirror for bit 3), one or two per
+    // 32-bit word, and the lane whose bit is b computes row b of the matrix:
+    // own M[b][b] + partner M[b][1-b] (c: the lane's two coefficients).
+    template <int B> static __device__ __forceinline__ uint32_t xor_lane_word(uint32_t w)
+    {
+        const int x = (int)w;
+        if constexpr (B == 0)
+            return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
+        else if constexpr (B == 1)
+            return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);
+        else if constexpr (B == 2)
+            return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true), 0x1B, 0xF,
+                                                      0xF, true);
+        else
+            return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true), 0x141, 0xF,
+                                                      0xF, true);
+    }
+    template <int B> static __device__ __forceinline__ R xor_lane(R a)
+    {
+        if constexpr (sizeof(R) == 8) {
+            auto w = __builtin_bit_cast(uint2, a);
+            w.x = xor_lane_word<B>(w.x);
+            w.y = xor_lane_word<B>(w.y);
+            return __builtin_bit_cast(R, w);
+        } else {
+            return __builtin_bit_cast(R, xor_lane_word<B>(__builtin_bit_cast(uint32_t, a)));
+        }
+    }
+    template <int B> static __device__ __forceinline__ void lane_gate(C (&v)[NR], const R (&c)[4])
+    {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const R px = xor_lane<B>(v[j].x), py = xor_lane<B>(v[j].y);
+            const R ox = v[j].x, oy = v[j].y;
+            v[j].x = fmadd(c[0], ox, fmadd(-c[1], oy, fmadd(c[2], px, -c[3] * py)));
+            v[j].y = fmadd(c[0], oy, fmadd(c[1], ox, fmadd(c[2], py, c[3] * px)));
+        }
+    }
+    static __device__ __forceinline__ void dispatch_lane_gate(uint32_t b, uint32_t tid, C (&v)[NR], const double *m)
+    {
+        const bool hi = ((tid >> b) & 1u) != 0;
+        const R c[4] = {(R)(hi ? m[6] : m[0]), (R)(hi ? m[7] : m[1]), (R)(hi ? m[4] : m[2]), (R)(hi ? m[5] : m[3])};
+        if (b == 0)
+            lane_gate<0>(v, c);
+        else if (b == 1)
+            lane_gate<1>(v, c);
+        else if (b == 2)
+            lane_gate<2>(v, c);
+        else
+            lane_gate<3>(v, c);
+    }
+
     // flip the sign bit where sg has it set (sg is 0 or the sign mask)
     static __device__ __forceinline__ R flip_sign(R x, uint32_t sg)
     {
@@ -451,24 +507,36 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
 
     // Re-layout (tbase, so, fl) -> (tbase2, so2, no flips) through LDS, one
     // component per round with HALF.
+    // With wave_local the two layouts put the same tile bits on the
+    // wavefront-index bits of the thread id: each wavefront reads back only
+    // LDS slots it wrote, in order, so only the compiler is kept from
+    // reordering the accesses.  Every other re-layout ends with a barrier, so
+    // a wavefront-local one never overlaps another wavefront's reads of the
+    // slots it writes.
     static __device__ __forceinline__ void relayout(unsigned char *lds, C (&v)[NR], uint32_t tbase,
                                                     const SlotOffs &so, uint32_t fl, uint32_t tbase2,
-                                                    const SlotOffs &so2)
+                                                    const SlotOffs &so2, bool wave_local = false)
     {
+        auto sync = [&] {
+            if (wave_local)
+                __asm__ __volatile__("" ::: "memory");
+            else
+                lds_sync();
+        };
         if constexpr (HALF) {
             to_lds<0>(lds, v, tbase, so, fl);
-            lds_sync();
+            sync();
             from_lds<0>(lds, v, tbase2, so2);
-            lds_sync();
+            sync();
             to_lds<1>(lds, v, tbase, so, fl);
-            lds_sync();
+            sync();
             from_lds<1>(lds, v, tbase2, so2);
-            lds_sync();
+            sync();
         } else {
             to_lds<2>(lds, v, tbase, so, fl);
-            lds_sync();
+            sync();
             from_lds<2>(lds, v, tbase2, so2);
-            lds_sync();
+            sync();
         }
     }
 
@@ -629,7 +697,7 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
                 } else if (kind == OP_REMAP) {
                     const SlotOffs so2 = offs_of(cur.w);
                     const uint32_t tbase2 = lane_bits(cur.hbit, tid);
-                    relayout(lds, v, tbase, so, fl, tbase2, so2);
+                    relayout(lds, v, tbase, so, fl, tbase2, so2, (cur.aux & REMAP_WAVE_LOCAL) != 0);
                     so = so2;
                     tbase = tbase2;
                     fl = 0;
@@ -643,6 +711,8 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
 #pragma unroll
                     for (int q = 0; q < LOG_R; ++q)
                         so.o[q] = q == slot ? o_new : so.o[q];
+                } else if (kind == OP_LANE) {
+                    dispatch_lane_gate(cur.tlane, tid, v, cur.m);
                 } else if ((base & cur.hmask) == cur.hmask) {
                     const uint32_t rm = cur.rmask, lm = cur.lmask;
                     const uint32_t rv = rm & ~fl;

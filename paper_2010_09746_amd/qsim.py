@@ -219,10 +219,13 @@ def _ints(x) -> np.ndarray:
 
 
 QS_OPT_FULL_MATRICES = 1
+QS_OPT_LANE_GATES = 2
+QS_OPT_LANE_GATES_WIDE = 4
+QS_OPT_LANE_EAGER = 8
 
 
 def make_opts(form="pass", k_tile=12, max_swaps=1, pinned=0, perm_exec="move", max_fuse=0,
-              reg_bits=0, full_matrices=False) -> qs_run_opts:
+              reg_bits=0, full_matrices=False, lane_gates=0, lane_eager=False) -> qs_run_opts:
     o = qs_run_opts()
     o.form = {"plain": QS_FORM_PLAIN, "pass": QS_FORM_PASS}.get(form, form)
     o.k_tile = k_tile
@@ -231,7 +234,11 @@ def make_opts(form="pass", k_tile=12, max_swaps=1, pinned=0, perm_exec="move", m
     o.perm_exec = {"move": QS_PERM_MOVE, "relabel": QS_PERM_RELABEL}.get(perm_exec, perm_exec)
     o.max_fuse = max_fuse
     o.reg_bits = reg_bits
-    o.flags = QS_OPT_FULL_MATRICES if full_matrices else 0
+    if lane_gates not in (0, 2, 4):
+        raise ValueError("lane_gates: 0, 2 or 4 thread bits")
+    o.flags = ((QS_OPT_FULL_MATRICES if full_matrices else 0)
+               | {0: 0, 2: QS_OPT_LANE_GATES, 4: QS_OPT_LANE_GATES_WIDE}[lane_gates]
+               | (QS_OPT_LANE_EAGER if lane_eager else 0))
     return o
 
 
@@ -319,7 +326,8 @@ def qs_program_get_stats(h: int) -> dict:
 
 
 OPC_NAMES = ["tile_pass", "u", "u_ctrl", "x_reg", "x_lane", "neg", "diag", "remap", "dispatch", "plain_u",
-             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction", "shear", "phase", "lswap"]
+             "plain_cu", "plain_cx", "plain_cz", "move", "move_fraction", "shear", "phase", "lswap", "lane",
+             "remap_wave"]
 
 
 def qs_program_op_counts(h: int) -> dict:

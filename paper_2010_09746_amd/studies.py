@@ -194,9 +194,11 @@ def ablation_study(n: int = 30, dtype: str = "c128", layers: int = 40, reps: int
     printed (r = 1, no pinned qubits; each PermuteQubits moves the data, so
     tiles stay contiguous), r = 1 with 3 pinned positions and relabelled
     placements, the fused pass with bundled exchanges (r = 16) over tile sizes
-    ks, and fusion without the pass (r = 0: gates on the first k positions
-    fused, every other gate one launch).  Device time of one run of the
-    compiled program each."""
+    ks, fusion without the pass (r = 0: gates on the first k positions
+    fused, every other gate one launch), and the pass at k_ref with one-qubit
+    gates on the lowest thread bits run through lane exchanges instead of
+    register re-layouts.  Device time of one run of the compiled program
+    each."""
     from . import costmodel
     from workloads import config_circuit
 
@@ -205,13 +207,22 @@ def ablation_study(n: int = 30, dtype: str = "c128", layers: int = 40, reps: int
                 ("Algorithm 1 (r=1), moved", dict(k_tile=k_ref, max_swaps=1, pinned=0, perm_exec="move")),
                 ("r=1, 3 pinned, relabelled", dict(k_tile=k_ref, max_swaps=1, pinned=3, perm_exec="relabel"))]
     variants += [(f"pass r={r} k={k}", dict(k_tile=k, max_swaps=r, pinned=3, perm_exec="relabel")) for k in ks]
+    # gates on the lowest thread bits through lane exchanges instead of
+    # register re-layouts (off by default)
+    lane = dict(k_tile=k_ref, max_swaps=r, pinned=3, perm_exec="relabel")
+    variants += [(f"pass r={r} k={k_ref}, lane gates on thread bits 0-3 when a re-layout is put off",
+                  dict(lane, lane_gates=4)),
+                 (f"pass r={r} k={k_ref}, lane gates on thread bits 0-1 whenever ready",
+                  dict(lane, lane_gates=2, lane_eager=True)),
+                 (f"pass r={r} k={k_ref}, lane gates on thread bits 0-3 whenever ready",
+                  dict(lane, lane_gates=4, lane_eager=True))]
     rows = []
     for name, o in variants:
         prog = Q.Program(g, n, dtype, form="pass", **o)
-        stt = prog.stats()
+        stt, cnt = prog.stats(), prog.op_counts()
         prog.close()
         ms = costmodel.measure_ms(g, n, dtype, o, reps=reps)
         rows.append(dict(variant=name, opts=o, ms=ms, amp_updates_per_s=len(g) * float(1 << n) / (ms * 1e-3),
                          n_perm=stt["n_perm"], n_global=stt["n_global"], n_tile_passes=stt["n_tile_passes"],
-                         n_plain=stt["n_plain"]))
+                         n_plain=stt["n_plain"], n_remaps=stt["n_remaps"], lane_gates=cnt["lane"]))
     return {"n": n, "dtype": dtype, "gates": int(len(g)), "rows": rows}

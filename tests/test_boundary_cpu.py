@@ -190,6 +190,63 @@ def test_op_counts_classify_tile_work():
     assert cp["plain_u"] == 3 and cp["plain_cx"] == 2 and cp["tile_pass"] == 0
 
 
+def test_lane_gate_options():
+    """Lane gates (uncontrolled one-qubit gates on the lowest thread bits run
+    through lane exchanges instead of waiting for a re-layout): off by
+    default; each one-qubit gate of the 30-qubit workload is still one
+    operation (a shear, a whole gate or a lane gate); running them whenever
+    ready saves re-layouts, more with four thread bits than with two; gates
+    with controls never take the lane form; unknown flag bits are rejected."""
+    g = config_circuit(2)
+    n_u = int(np.sum(g["kind"] == KIND_U))
+    base = dict(form="pass", k_tile=12, max_swaps=16, pinned=3, perm_exec="relabel")
+    res = {}
+    for lanes, eager in ((0, False), (4, False), (2, True), (4, True)):
+        P = Q.Program(g, 30, "c128", lane_gates=lanes, lane_eager=eager, **base)
+        res[(lanes, eager)] = (P.op_counts(), P.stats())
+        P.close()
+    for c, st in res.values():
+        assert c["shear"] + c["u"] + c["lane"] == n_u
+        assert st["n_tile_passes"] == 43
+    assert res[(0, False)][0]["lane"] == 0
+    assert 0 < res[(2, True)][0]["lane"] < res[(4, True)][0]["lane"]
+    assert res[(4, True)][1]["n_remaps"] < res[(2, True)][1]["n_remaps"] < res[(0, False)][1]["n_remaps"]
+    two = mixed_circuit(14, 400, seed=3)
+    two = two[two["kind"] != KIND_U]
+    P = Q.Program(two, 14, "c128", form="pass", k_tile=10, max_swaps=4, lane_gates=4, lane_eager=True)
+    assert P.op_counts()["lane"] == 0
+    P.close()
+    with pytest.raises(ValueError):
+        Q.make_opts(lane_gates=3)
+    o = Q.make_opts(**base)
+    o.flags = 16
+    with pytest.raises(Q.QsimError):
+        Q.qs_compile(g[:10], 30, "c128", None, o)
+
+
+def test_wavefront_local_relayouts():
+    """Re-layouts that keep the tile bits on the wavefront bits of the thread
+    id need no barrier.  On the 30-qubit workload (four wavefronts per
+    workgroup) the choice of those bits by next use makes 81 of the 129
+    re-layouts inside passes wavefront-local (the first layout of a pass never
+    is); a workgroup of one wavefront has none to keep, and with lane gates
+    (which name thread bits of the ascending map) none are made."""
+    g = config_circuit(2)
+    base = dict(form="pass", k_tile=12, max_swaps=16, pinned=3, perm_exec="relabel")
+    P = Q.Program(g, 30, "c128", **base)
+    c, st = P.op_counts(), P.stats()
+    P.close()
+    assert c["remap"] == 172 and c["remap_wave"] == 81
+    assert c["remap_wave"] <= c["remap"] - st["n_tile_passes"]
+    P = Q.Program(g, 30, "c128", lane_gates=2, **base)
+    assert P.op_counts()["remap_wave"] == 0
+    P.close()
+    P = Q.Program(g[:200], 30, "c128", form="pass", k_tile=8, reg_bits=2, max_swaps=4)
+    c = P.op_counts()
+    P.close()
+    assert c["remap"] > 0 and c["remap_wave"] == 0
+
+
 def test_cost_model_prediction_is_linear_in_counts():
     from paper_2010_09746_amd.costmodel import TILE_CLASSES, CostModel
     cm = CostModel("c128", n_cal=20)

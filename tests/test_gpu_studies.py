@@ -98,8 +98,11 @@ def test_kernel_sweep_small():
 def test_ablation_study_small():
     r = studies.ablation_study(n=16, layers=8, ks=(10, 14), k_ref=10, r=8)
     rows = {x["variant"]: x for x in r["rows"]}
-    assert set(rows) == {"fusion without pass", "Algorithm 1 (r=1), moved", "r=1, 3 pinned, relabelled",
-                         "pass r=8 k=10", "pass r=8 k=14"}
+    lane = {k for k in rows if "lane gates" in k}
+    assert set(rows) - lane == {"fusion without pass", "Algorithm 1 (r=1), moved", "r=1, 3 pinned, relabelled",
+                                "pass r=8 k=10", "pass r=8 k=14"}
+    assert len(lane) == 3 and all(rows[k]["opts"]["k_tile"] == 10 for k in lane)
+    assert max(rows[k]["lane_gates"] for k in lane) > 0
     nopass = rows["fusion without pass"]
     assert nopass["n_perm"] == 0 and nopass["n_global"] > 0 and nopass["n_plain"] == nopass["n_global"]
     alg1 = rows["Algorithm 1 (r=1), moved"]
