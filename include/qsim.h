@@ -123,8 +123,21 @@ enum { QS_PERM_MOVE = 0, QS_PERM_RELABEL = 1 };
  *              ready.  Off by default: on the 30-qubit layered workload they
  *              cost more than the re-layouts they save.  Same result up to
  *              rounding.
+ *              QS_OPT_FROM_ZERO: the run starts from |0...0> whatever the
+ *              state holds (its placement still has to be the starting
+ *              one).  When the first launch is a tile pass it generates the
+ *              basis state in registers instead of reading the state (no
+ *              preparation pass over HBM); otherwise the state is set to
+ *              |0...0> first.  For qs_compile the flag is kept with the
+ *              program and applies to every qs_run_program of it.
  */
-enum { QS_OPT_FULL_MATRICES = 1, QS_OPT_LANE_GATES = 2, QS_OPT_LANE_GATES_WIDE = 4, QS_OPT_LANE_EAGER = 8 };
+enum {
+    QS_OPT_FULL_MATRICES = 1,
+    QS_OPT_LANE_GATES = 2,
+    QS_OPT_LANE_GATES_WIDE = 4,
+    QS_OPT_LANE_EAGER = 8,
+    QS_OPT_FROM_ZERO = 16
+};
 typedef struct {
     int32_t form;
     int32_t k_tile;

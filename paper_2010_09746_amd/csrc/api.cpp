@@ -362,11 +362,18 @@ void upload_ops(Program &p)
     p.dev = dev;
 }
 
-// Enqueue launches [a, b) of p; tile operations are read from d_ops.
+// Enqueue launches [a, b) of p; tile operations are read from d_ops.  A
+// program run from |0...0> (QS_OPT_FROM_ZERO) has its first tile pass start
+// from the basis state in registers; any other first launch gets the state
+// set first.
 void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, const TileOp *d_ops)
 {
+    const bool from_zero = (p.opts.flags & QS_OPT_FROM_ZERO) != 0;
     for (size_t li = a_idx; li < b_idx; ++li) {
         const Launch &L = p.launches[li];
+        const bool basis = from_zero && li == 0;
+        if (basis && L.type != L_TILE)
+            timed(s->stream, P_BASIS, (double)s->bytes, [&] { launch_set_basis(s->buf, s->dt, s->n, 0, s->stream); });
         switch (L.type) {
         case L_PLAIN:
             timed(s->stream, gate_class(L.gate.kind), gate_bytes(L.gate.kind, s->n, elem_bytes(s->dt)),
@@ -381,6 +388,8 @@ void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, con
             a.state = s->buf;
             a.ops = d_ops + L.op_begin;
             a.n_hi = s->n - L.k;
+            if (basis)
+                a.io |= IO_BASIS;
             const uint64_t tiles = 1ull << (s->n - L.k);
             timed(s->stream, P_TILE, 2.0 * (double)s->bytes, [&] {
                 if (s->dt == QS_C64)
@@ -402,11 +411,19 @@ void check_program_fits(const qs_state *s, const Program &p)
         fail(QS_ERR_STATE, "state placement differs from the program's starting placement");
 }
 
+// A program with no launch run from |0...0> still sets the state.
+void finish_empty(qs_state *s, const Program &p)
+{
+    if ((p.opts.flags & QS_OPT_FROM_ZERO) && p.launches.empty())
+        timed(s->stream, P_BASIS, (double)s->bytes, [&] { launch_set_basis(s->buf, s->dt, s->n, 0, s->stream); });
+}
+
 void run_launches(qs_state *s, Program &p)
 {
     check_program_fits(s, p);
     upload_ops(p);
     launch_range(s, p, 0, p.launches.size(), p.d_ops);
+    finish_empty(s, p);
     s->sigma = p.sigma_final;
 }
 
@@ -454,6 +471,7 @@ void run_program_with_ops(qs_state *s, const Program &p, const TileOp *d_ops)
 {
     check_program_on(s, p);
     launch_range(s, p, 0, p.launches.size(), d_ops);
+    finish_empty(s, p);
     s->sigma = p.sigma_final;
 }
 
@@ -862,6 +880,7 @@ qs_status run_circuit_entry(qs_state *s, const qs_gate *gates, int64_t n_gates, 
                 (void)hipStreamSynchronize(s->stream);
                 throw;
             }
+            finish_empty(s, p);
             s->sigma = p.sigma_final;
         } else {
             compile_program(gates, n_gates, s->n, s->dt, s->sigma.data(), o, p);

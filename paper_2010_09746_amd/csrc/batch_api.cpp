@@ -388,7 +388,7 @@ qs_status qs_batch_create(int count, const int *n_qubits, const qs_gate *const *
                 D.t.state = static_cast<char *>(b->d_state) + b->start[c] * eb;
                 D.t.n_hi = b->n[c] - P.k;
                 if (P.level == 0)
-                    D.t.io |= 16u;  // the first pass starts from |0...0> instead of reading the state
+                    D.t.io |= IO_BASIS;  // the first pass starts from |0...0> instead of reading the state
                 D.ntiles = P.tiles;
                 D.last = P.last;
                 D.zpos = bp.progs[c].sigma_final[0];

@@ -1274,6 +1274,9 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         fail(QS_ERR_ARG, "n out of range");
     p.n = n;
     p.dt = dt;
+    if (o.flags & ~(QS_OPT_FULL_MATRICES | QS_OPT_LANE_GATES | QS_OPT_LANE_GATES_WIDE | QS_OPT_LANE_EAGER |
+                    QS_OPT_FROM_ZERO))
+        fail(QS_ERR_ARG, "unknown flags");
     p.opts = o;
     p.sigma0.resize(n);
     for (int q = 0; q < n; ++q)
@@ -1353,8 +1356,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
             fail(QS_ERR_ARG, "pinned must be in [0, k_tile]");
         if (o.perm_exec != QS_PERM_MOVE && o.perm_exec != QS_PERM_RELABEL)
             fail(QS_ERR_ARG, "unknown perm_exec");
-        if (o.flags & ~(QS_OPT_FULL_MATRICES | QS_OPT_LANE_GATES | QS_OPT_LANE_GATES_WIDE | QS_OPT_LANE_EAGER))
-            fail(QS_ERR_ARG, "unknown flags");
+
         // tile passes need 7 <= k and a tile that fits in one CU's LDS; a larger
         // local set (e.g. a pass planned for several devices) runs its
         // segments gate by gate

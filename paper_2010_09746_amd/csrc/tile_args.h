@@ -36,6 +36,7 @@ enum TileOpKind : int32_t {
 };
 
 constexpr uint32_t REMAP_WAVE_LOCAL = 1u;
+constexpr uint32_t IO_BASIS = 16u;
 
 // One operation of a fused tile pass (104 bytes, every field at least 32 bits
 // wide and naturally aligned so that the kernel reads it with scalar loads).  Its controls are split by
@@ -94,7 +95,9 @@ struct TileArgs {
                                   // t is stored at index sperm(t) (a bit permutation);
                                   // bit 3: the lowest tile positions are the lowest
                                   // physical positions, so every load and store moves
-                                  // whole 128-byte lines (non-temporal access pays)
+                                  // whole 128-byte lines (non-temporal access pays);
+                                  // bit 4 (IO_BASIS): nothing is read, the tiles start as
+                                  // the basis state |0...0> (1 at physical index 0)
     int32_t pad;
     uint8_t sperm[16];            // tile bit b moves to tile bit sperm[b] (io bit 2)
 };

@@ -879,7 +879,7 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint64_t t = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    TileKernel<R, LOG_NT, LOG_R, true, STREAM>::template run_range<false>(a, lds_raw, t, t + 1, 1, {nullptr, 0});
+    TileKernel<R, LOG_NT, LOG_R, true, STREAM>::template run_range<false, true>(a, lds_raw, t, t + 1, 1, {nullptr, 0});
 }
 
 template <typename R, int LOG_NT, int LOG_R, bool STREAM>
