@@ -391,7 +391,8 @@ void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, con
             if (basis)
                 a.io |= IO_BASIS;
             const uint64_t tiles = 1ull << (s->n - L.k);
-            timed(s->stream, P_TILE, 2.0 * (double)s->bytes, [&] {
+            // a pass from the basis state reads nothing
+            timed(s->stream, P_TILE, (basis ? 1.0 : 2.0) * (double)s->bytes, [&] {
                 if (s->dt == QS_C64)
                     launch_tile_f32(a, tiles, L.log_r, L.log_nt, s->stream);
                 else
