@@ -317,6 +317,19 @@ qs_status qs_run_circuit(qs_state *s, const qs_gate *gates, int64_t n_gates,
 qs_status qs_run_circuit_costed(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
                                 const qs_pass_costs *costs);
 
+/* qs_run_circuit (costs NULL) or qs_run_circuit_costed, then <Z_q> of the
+ * final state as qs_expect_z gives it (Section 2: measurement), with the
+ * read-out folded into the last launch: when that launch is a tile pass it
+ * also writes, per tile, the sum of |a|^2 and the sums over the amplitudes
+ * whose bit is 1 at each of the tile's positions (FP64, fixed order), and a
+ * small kernel folds them into the per-position sums, so no read-out pass
+ * over the state runs; otherwise the read-out pass of qs_expect_z follows.
+ * The last launch is enqueued once the program is complete.  expect_z: host,
+ * n doubles (logical qubit order).  Same results as qs_run_circuit followed by
+ * qs_expect_z, up to the order of the FP64 additions. */
+qs_status qs_run_circuit_expect_z(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
+                                  const qs_pass_costs *costs, double *expect_z);
+
 /* ---- allocation-free run -------------------------------------------------- */
 
 /* Tile operations a program run by qs_run_program_noalloc may hold. */

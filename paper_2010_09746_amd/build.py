@@ -18,8 +18,10 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libqsim.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["api.cpp", "batch_api.cpp", "server_api.cpp", "gates.hip", "readout.hip", "tile_f32.hip", "tile_f64.hip",
-               "batch_f32.hip", "batch_f64.hip", "noalloc.hip"]
+# the tile-pass units first: they take minutes each and compile in parallel
+HIP_SOURCES = ["tile_f64.hip", "tile_f64_plain.hip", "tile_f64_z.hip", "tile_f32.hip", "tile_f32_plain.hip",
+               "tile_f32_z.hip", "batch_f64.hip", "batch_f32.hip", "api.cpp", "batch_api.cpp", "server_api.cpp",
+               "gates.hip", "readout.hip", "noalloc.hip"]
 CXX_SOURCES = ["compiler.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

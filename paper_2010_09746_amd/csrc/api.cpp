@@ -90,9 +90,9 @@ void need(bool cond, const char *msg)
 // launch profiling: HIP events recorded on the launching stream around each
 // launch, resolved when read
 
-enum ProfClass { P_TILE, P_U, P_CU, P_CX, P_CZ, P_MOVE, P_BASIS, P_ZSUM, P_GATHER, P_FID, P_NCLASS };
+enum ProfClass { P_TILE, P_U, P_CU, P_CX, P_CZ, P_MOVE, P_BASIS, P_ZSUM, P_GATHER, P_FID, P_ZFOLD, P_NCLASS };
 const char *const PROF_NAMES[P_NCLASS] = {"tile_pass", "plain_u", "plain_cu", "plain_cx", "plain_cz",
-                                          "move_involution", "set_basis", "zsum", "gather", "fidelity"};
+                                          "move_involution", "set_basis", "zsum", "gather", "fidelity", "zfold"};
 
 struct ProfRec {
     int cls;
@@ -366,7 +366,8 @@ void upload_ops(Program &p)
 // program run from |0...0> (QS_OPT_FROM_ZERO) has its first tile pass start
 // from the basis state in registers; any other first launch gets the state
 // set first.
-void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, const TileOp *d_ops)
+void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, const TileOp *d_ops,
+                  double *zparts = nullptr)
 {
     const bool from_zero = (p.opts.flags & QS_OPT_FROM_ZERO) != 0;
     for (size_t li = a_idx; li < b_idx; ++li) {
@@ -393,7 +394,11 @@ void launch_range(qs_state *s, const Program &p, size_t a_idx, size_t b_idx, con
             const uint64_t tiles = 1ull << (s->n - L.k);
             // a pass from the basis state reads nothing
             timed(s->stream, P_TILE, (basis ? 1.0 : 2.0) * (double)s->bytes, [&] {
-                if (s->dt == QS_C64)
+                if (zparts && s->dt == QS_C64)
+                    launch_tile_f32_z(a, tiles, L.log_r, L.log_nt, zparts, s->stream);
+                else if (zparts)
+                    launch_tile_f64_z(a, tiles, L.log_r, L.log_nt, zparts, s->stream);
+                else if (s->dt == QS_C64)
                     launch_tile_f32(a, tiles, L.log_r, L.log_nt, s->stream);
                 else
                     launch_tile_f64(a, tiles, L.log_r, L.log_nt, s->stream);
@@ -826,12 +831,95 @@ qs_status qs_run_program(qs_state *s, const qs_program *p)
     });
 }
 
+static void zsum(qs_state *s, std::vector<double> &res);
+
 // Compile and run.  In the pass form the launches of each segment are
 // enqueued as soon as the pass has fixed it, so the device works on the first
-// segments while the host is still choosing later permutations.
+// segments while the host is still choosing later permutations.  With ez the
+// last launch is held back until the program is complete: when it is a tile
+// pass it also writes per-tile probability sums, folded into the sums of
+// qs_expect_z (no read-out pass over the state); otherwise the read-out pass
+// runs after it.  ez receives <Z_q> (host, n doubles).
 namespace {
+// Launches [from, end) of a complete program, then <Z_q> into ez.  When the
+// last tile pass moves whole lines and every launch after it is a CNOT or CZ
+// on its own, that pass writes its per-tile sums: a CZ leaves every bit's
+// probability alone and a CNOT makes its target bit the XOR of target and
+// control, so each final bit is an XOR of bits after the pass, folded from
+// those sums (when at most one of the XORed bits is a tile bit).  Otherwise
+// the read-out pass runs after the last launch.
+void fused_expect_z(qs_state *s, const Program &p, const TileOp *d_ops, size_t from, double *ez)
+{
+    const size_t end = p.launches.size();
+    size_t lt = end;
+    for (size_t li = end; li-- > from;)
+        if (p.launches[li].type == L_TILE) {
+            lt = li;
+            break;
+        }
+    bool fold = lt < end && (p.launches[lt].io & 8u) && !(p.launches[lt].io & 4u);
+    // bit p after the program = XOR of the bits in mask[p] after the pass
+    std::vector<uint64_t> mask(s->n);
+    for (int q = 0; q < s->n; ++q)
+        mask[q] = 1ull << q;
+    for (size_t li = lt + 1; fold && li < end; ++li) {
+        const Launch &L = p.launches[li];
+        if (L.type != L_PLAIN || (L.gate.kind != QS_GATE_CX && L.gate.kind != QS_GATE_CZ))
+            fold = false;
+        else if (L.gate.kind == QS_GATE_CX)
+            mask[L.gate.q1] ^= mask[L.gate.q0];
+    }
+    ZFoldMap m{};
+    if (fold) {
+        const Launch &L = p.launches[lt];
+        std::vector<int> layout(s->n, 0), rank(s->n, -1);
+        for (int q = 0; q < L.log_r; ++q)
+            layout[L.st_reg[q]] = 1 + q;
+        for (int i = 0; i < L.log_nt; ++i)
+            layout[L.st_lane[i]] = 1 + L.log_r + i;
+        for (int pos = 0, r = 0; pos < s->n; ++pos)
+            if (!layout[pos])
+                rank[pos] = r++;
+        for (int pos = 0; pos < s->n && fold; ++pos) {
+            m.v[pos] = 0;
+            m.rm[pos] = 0;
+            for (int b = 0; b < s->n; ++b) {
+                if (!((mask[pos] >> b) & 1u))
+                    continue;
+                if (layout[b]) {
+                    fold = m.v[pos] == 0;  // at most one tile bit
+                    m.v[pos] = layout[b];
+                } else {
+                    m.rm[pos] |= 1ull << rank[b];
+                }
+            }
+        }
+    }
+    std::vector<double> r(s->n + 1);
+    if (fold) {
+        const Launch &L = p.launches[lt];
+        const int nv = 1 + L.log_r + L.log_nt;
+        const uint64_t tiles = 1ull << (s->n - L.k);
+        ensure_work(s, (size_t)tiles * nv + (size_t)s->n + 1);
+        double *parts = s->d_work, *outd = s->d_work + (size_t)tiles * nv;
+        launch_range(s, p, from, lt, d_ops);
+        launch_range(s, p, lt, lt + 1, d_ops, parts);
+        launch_range(s, p, lt + 1, end, d_ops);
+        timed(s->stream, P_ZFOLD, (double)tiles * nv * sizeof(double),
+              [&] { launch_zfold(parts, tiles, nv, s->n, m, outd, s->stream); });
+        hipchk(hipMemcpyAsync(r.data(), outd, (s->n + 1) * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+               "hipMemcpyAsync");
+        hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    } else {
+        launch_range(s, p, from, end, d_ops);
+        zsum(s, r);
+    }
+    for (int q = 0; q < s->n; ++q)
+        ez[q] = r[0] - 2.0 * r[1 + p.sigma_final[q]];
+}
+
 qs_status run_circuit_entry(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
-                            const qs_pass_costs *costs)
+                            const qs_pass_costs *costs, double *ez = nullptr)
 {
     return guard([&] {
         need(s != nullptr, "state is NULL");
@@ -868,8 +956,19 @@ qs_status run_circuit_entry(qs_state *s, const qs_gate *gates, int64_t n_gates, 
                        "hipMemcpyAsync(tile ops)");
                 uploaded = pp.ops.size();
             }
-            launch_range(s, pp, launched, pp.launches.size(), s->d_ops);
-            launched = pp.launches.size();
+            // with ez the newest tile pass and the launches after it wait:
+            // that pass may be the one that folds in the read-out
+            size_t upto = pp.launches.size();
+            if (ez)
+                for (size_t li = upto; li-- > launched;)
+                    if (pp.launches[li].type == L_TILE) {
+                        upto = li;
+                        break;
+                    }
+            if (upto > launched) {
+                launch_range(s, pp, launched, upto, s->d_ops);
+                launched = upto;
+            }
         };
         if (o.form == QS_FORM_PASS) {
             try {
@@ -881,6 +980,15 @@ qs_status run_circuit_entry(qs_state *s, const qs_gate *gates, int64_t n_gates, 
                 (void)hipStreamSynchronize(s->stream);
                 throw;
             }
+            if (ez && launched < p.launches.size()) {
+                try {
+                    fused_expect_z(s, p, s->d_ops, launched, ez);
+                } catch (...) {
+                    (void)hipStreamSynchronize(s->stream);
+                    throw;
+                }
+                ez = nullptr;
+            }
             finish_empty(s, p);
             s->sigma = p.sigma_final;
         } else {
@@ -891,6 +999,12 @@ qs_status run_circuit_entry(qs_state *s, const qs_gate *gates, int64_t n_gates, 
                 (void)hipStreamSynchronize(s->stream);
                 throw;
             }
+        }
+        if (ez) {
+            std::vector<double> r;
+            zsum(s, r);
+            for (int q = 0; q < s->n; ++q)
+                ez[q] = r[0] - 2.0 * r[1 + s->sigma[q]];
         }
         // the tables (and the staging the copies read) are reused next call
         hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
@@ -909,6 +1023,14 @@ qs_status qs_run_circuit_costed(qs_state *s, const qs_gate *gates, int64_t n_gat
     if (!costs)
         return guard([&] { need(false, "costs is NULL"); });
     return run_circuit_entry(s, gates, n_gates, opts, costs);
+}
+
+qs_status qs_run_circuit_expect_z(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
+                                  const qs_pass_costs *costs, double *expect_z)
+{
+    if (!expect_z)
+        return guard([&] { need(false, "expect_z is NULL"); });
+    return run_circuit_entry(s, gates, n_gates, opts, costs, expect_z);
 }
 
 qs_status qs_synchronize(qs_state *s)

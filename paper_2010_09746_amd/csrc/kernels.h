@@ -23,6 +23,16 @@ void launch_involution(void *state, qs_dtype dt, int n, const std::vector<int> &
 // One fused tile pass.
 void launch_tile_f32(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st);
 void launch_tile_f64(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st);
+// the passes that do not move whole 128-byte lines (plain loads and stores)
+void launch_tile_f32_plain(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st);
+void launch_tile_f64_plain(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st);
+// The same, each tile also writing its per-bit probability sums to zparts
+// (1 + log_r + log_nt doubles per tile, see run_range's ZB read-out); passes
+// over whole 128-byte lines only (TileArgs::io bit 3).
+void launch_tile_f32_z(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, double *zparts,
+                       hipStream_t st);
+void launch_tile_f64_z(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, double *zparts,
+                       hipStream_t st);
 
 // Batching form.  All states |0> (element offsets of each circuit's first
 // amplitude in starts_dev), one persistent launch per pass level, then the
@@ -48,6 +58,21 @@ constexpr int QUEUE_MIN_SHAPE = 1, QUEUE_MAX_SHAPE = 4, QUEUE_LOG_NT = 8;
 size_t zsum_work_doubles(int n);
 void launch_zsum(const void *state, qs_dtype dt, int n, double *work_dev, double *out_dev,
                  hipStream_t st);
+
+// The same sums from the per-tile read-out of a tile pass (zparts of
+// launch_tile_f32_z/f64_z, nv doubles per tile: T, then B_v for v = 1..nv-1,
+// the bits of the pass's store layout, slot bits first).  Output 1 + p sums,
+// over tiles t, the probability that bit p is 1 where that bit is the XOR of
+// the layout bit v[p] (none when v[p] < 1) and of the bits of the tile index
+// in rm[p]: B_v or T - B_v by the parity of t & rm[p], or T or 0 without a
+// layout bit.  (Bit p of the state after a pass and some CNOTs is such an
+// XOR of bits before them.)
+struct ZFoldMap {
+    int32_t v[64];
+    uint64_t rm[64];
+};
+void launch_zfold(const double *parts, uint64_t tiles, int nv, int n, const ZFoldMap &m, double *out_dev,
+                  hipStream_t st);
 
 // out_dev[2i], out_dev[2i+1] = amplitude at physical index idx_dev[i] (FP64).
 void launch_gather(const void *state, qs_dtype dt, const uint64_t *idx_dev, int64_t count,

@@ -104,6 +104,38 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double *part, uint64_t 
         out[o] = red[0];
 }
 
+// Fold the per-tile read-out of a tile pass into the sums of k_zsum (see
+// ZFoldMap): output 0 is the sum over tiles of T, output 1 + p that of the
+// probability of bit p.  Thread t of a block takes tiles t (mod 256) in order,
+// then the 256 sums are added in a fixed tree.
+__global__ __launch_bounds__(256) void k_zfold(const double *parts, uint64_t tiles, int nv, ZFoldMap m, double *out)
+{
+    __shared__ double red[256];
+    const int o = blockIdx.x;
+    const int v = o == 0 ? 0 : m.v[o - 1];
+    const uint64_t rm = o == 0 ? 0 : m.rm[o - 1];
+    double r = 0.0;
+    for (uint64_t t = threadIdx.x; t < tiles; t += 256) {
+        const double T = parts[t * nv];
+        const bool odd = (__popcll(t & rm) & 1) != 0;
+        if (o == 0)
+            r += T;
+        else if (v >= 1)
+            r += odd ? T - parts[t * nv + v] : parts[t * nv + v];
+        else if (odd)
+            r += T;
+    }
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[o] = red[0];
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(const Cplx<R> *__restrict__ s, const uint64_t *idx, int64_t count,
                                                 double *out)
@@ -229,6 +261,13 @@ void launch_zsum(const void *state, qs_dtype dt, int n, double *work, double *ou
     check_launch("zsum");
     hipLaunchKernelGGL(k_sum_parts, dim3(n + 1), dim3(256), 0, st, work, nb, n + 1, out);
     check_launch("zsum final");
+}
+
+void launch_zfold(const double *parts, uint64_t tiles, int nv, int n, const ZFoldMap &m, double *out_dev,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zfold, dim3(n + 1), dim3(256), 0, st, parts, tiles, nv, m, out_dev);
+    check_launch("zfold");
 }
 
 void launch_gather(const void *state, qs_dtype dt, const uint64_t *idx, int64_t count, double *out, hipStream_t st)

@@ -599,9 +599,16 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     // from kernel arguments or from device memory.  With BASIS, a pass whose
     // TileArgs::io has bit 4 set reads nothing: its tiles start as the basis
     // state |0...0> (1 at physical index 0, 0 elsewhere).
-    template <bool PF, bool BASIS = false, typename A>
+    // With ZB each tile also writes NV = 1 + LOG_R + LOG_NT doubles to
+    // zparts + NV t: the sum of |a|^2 over the tile, then for each register
+    // slot bit and each thread-id bit of the store layout (positions st_reg,
+    // st_lane) the sum of |a|^2 over the amplitudes whose bit there is 1,
+    // reduced in a fixed order (wavefront butterflies, then the wavefronts in
+    // order).
+    static constexpr int NV = 1 + LOG_R + LOG_NT;
+    template <bool PF, bool BASIS = false, bool ZB = false, typename A>
     static __device__ __forceinline__ void run_range(const A &a, unsigned char *lds, uint64_t t_first, uint64_t t_end,
-                                                     uint64_t t_step, Readout ro)
+                                                     uint64_t t_step, Readout ro, double *zparts = nullptr)
     {
         C *st = reinterpret_cast<C *>(a.state);
         OpPtr ops = (OpPtr)(a.ops);
@@ -805,12 +812,24 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
             }
             C *dst = st + base + lane_st;
             double nrm = 0.0, z = 0.0;
+            double zt = 0.0, zu[LOG_R];
+#pragma unroll
+            for (int q = 0; q < LOG_R; ++q)
+                zu[q] = 0.0;
             for_slots<uint64_t>(pbit_st, [&](int j, uint64_t o) {
                 if constexpr (STREAM) {
                     __builtin_nontemporal_store(v[j].x, &dst[o ^ dfl].x);
                     __builtin_nontemporal_store(v[j].y, &dst[o ^ dfl].y);
                 } else {
                     dst[o ^ dfl] = v[j];
+                }
+                if constexpr (ZB) {
+                    const double re = (double)v[j].x, im = (double)v[j].y, p = re * re + im * im;
+                    zt += p;
+#pragma unroll
+                    for (int q = 0; q < LOG_R; ++q)
+                        if ((j >> q) & 1)
+                            zu[q] += p;
                 }
                 if (ro.out) {
                     const uint64_t phys = base + lane_st + (o ^ dfl);
@@ -821,6 +840,8 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
             });
             if (ro.out)
                 reduce_pair(nrm, z, ro.out + 2 * ((t - t_first) / t_step), reinterpret_cast<double *>(lds));
+            if constexpr (ZB)
+                reduce_bits(zt, zu, direct ? fl : 0u, zparts + (uint64_t)NV * t, reinterpret_cast<double *>(lds));
             lds_sync();  // the next tile reuses the LDS buffer
             if constexpr (PF) {
                 if (more) {
@@ -829,6 +850,42 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
                         v[j] = w[j];
                 }
             }
+        }
+    }
+
+    // The NV sums of the ZB read-out: slot bit q holds 1 where (j >> q) ^ (flips
+    // >> q) is 1 (a slot whose exchange was applied by relabelling counts the
+    // other half), thread bit i where the thread id has it.
+    static __device__ __forceinline__ void reduce_bits(double zt, const double (&zu)[LOG_R], uint32_t flips,
+                                                       double *out, double *red)
+    {
+        const uint32_t tid = threadIdx.x;
+        double zv[NV];
+        zv[0] = zt;
+#pragma unroll
+        for (int q = 0; q < LOG_R; ++q)
+            zv[1 + q] = ((flips >> q) & 1u) ? zt - zu[q] : zu[q];
+#pragma unroll
+        for (int i = 0; i < LOG_NT; ++i)
+            zv[1 + LOG_R + i] = ((tid >> i) & 1u) ? zt : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1)
+                zv[v] += __shfl_xor(zv[v], d);
+        // other wavefronts may still read LDS slots of a wavefront-local re-layout
+        lds_sync();
+        if ((tid & 63u) == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                red[(tid >> 6) * NV + v] = zv[v];
+        }
+        lds_sync();
+        if (tid < (uint32_t)NV) {
+            double r = 0.0;
+            for (int w = 0; w < (NT >> 6); ++w)
+                r += red[w * NV + tid];
+            out[tid] = r;
         }
     }
 
@@ -882,11 +939,22 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_tile(TileArgs a)
     TileKernel<R, LOG_NT, LOG_R, true, STREAM>::template run_range<false, true>(a, lds_raw, t, t + 1, 1, {nullptr, 0});
 }
 
+// The same pass with the ZB read-out of every tile into zparts.
 template <typename R, int LOG_NT, int LOG_R, bool STREAM>
-void launch_tile_kernel(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
+__global__ __launch_bounds__(1 << LOG_NT) void k_tile_z(TileArgs a, double *zparts)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint64_t t = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    TileKernel<R, LOG_NT, LOG_R, true, STREAM>::template run_range<false, true, true>(a, lds_raw, t, t + 1, 1,
+                                                                                       {nullptr, 0}, zparts);
+}
+
+template <typename R, int LOG_NT, int LOG_R, bool STREAM, bool ZB>
+void launch_tile_kernel(const TileArgs &a, uint64_t n_tiles, double *zparts, hipStream_t st)
 {
     constexpr size_t bytes = TileKernel<R, LOG_NT, LOG_R>::LDS_BYTES;
-    const void *fn = reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R, STREAM>);
+    const void *fn = ZB ? reinterpret_cast<const void *>(&k_tile_z<R, LOG_NT, LOG_R, STREAM>)
+                        : reinterpret_cast<const void *>(&k_tile<R, LOG_NT, LOG_R, STREAM>);
     // once per process (a thread-safe static initialisation); a failure
     // throws, and the next launch tries again
     static const bool ready = [fn] {
@@ -906,31 +974,38 @@ void launch_tile_kernel(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
     const uint64_t row = std::min<uint64_t>(n_tiles, (1ull << 31) >> LOG_NT);
     if (n_tiles % row != 0 || n_tiles / row > 0xffffull)
         fail(QS_ERR_UNSUPPORTED, "tile count does not fit one launch");
-    hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R, STREAM>), dim3((unsigned)row, (unsigned)(n_tiles / row)),
-                       dim3(1 << LOG_NT), bytes, st, a);
+    if constexpr (ZB)
+        hipLaunchKernelGGL((k_tile_z<R, LOG_NT, LOG_R, STREAM>), dim3((unsigned)row, (unsigned)(n_tiles / row)),
+                           dim3(1 << LOG_NT), bytes, st, a, zparts);
+    else
+        hipLaunchKernelGGL((k_tile<R, LOG_NT, LOG_R, STREAM>), dim3((unsigned)row, (unsigned)(n_tiles / row)),
+                           dim3(1 << LOG_NT), bytes, st, a);
     check_launch("tile pass");
 }
 
-template <typename R, int LOG_NT, int LOG_R>
-void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, hipStream_t st)
+// MODE 0: plain loads and stores; 1: non-temporal (passes over whole 128-byte
+// lines, TileArgs::io bit 3); 2: non-temporal with the per-tile read-out.
+// Each mode is instantiated in a translation unit of its own, so that the
+// three sets compile in parallel.
+template <typename R, int LOG_NT, int LOG_R, int MODE>
+void launch_tile_inst(const TileArgs &a, uint64_t n_tiles, double *zparts, hipStream_t st)
 {
-    if (a.io & 8u)
-        launch_tile_kernel<R, LOG_NT, LOG_R, true>(a, n_tiles, st);
-    else
-        launch_tile_kernel<R, LOG_NT, LOG_R, false>(a, n_tiles, st);
+    if (MODE != 0 && !(a.io & 8u))
+        fail(QS_ERR_UNSUPPORTED, "non-temporal tile pass over partial lines");
+    launch_tile_kernel<R, LOG_NT, LOG_R, MODE != 0, MODE == 2>(a, n_tiles, zparts, st);
 }
 
 // Dispatch over the instantiated shapes: 2^6..2^10 threads, 2..32 amplitudes
 // per thread, at most 128 KiB of LDS (half the tile).
-template <typename R>
-void launch_tile_t(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, hipStream_t st)
+template <typename R, int MODE>
+void launch_tile_t(const TileArgs &a, uint64_t n_tiles, int log_r, int log_nt, double *zparts, hipStream_t st)
 {
-#define QS_TILE_CASE(NTB, RB)                                          \
-    if (log_nt == NTB && log_r == RB) {                                \
-        if constexpr (TileKernel<R, NTB, RB>::LDS_BYTES <= 131072) {    \
-            launch_tile_inst<R, NTB, RB>(a, n_tiles, st);              \
-            return;                                                    \
-        }                                                              \
+#define QS_TILE_CASE(NTB, RB)                                            \
+    if (log_nt == NTB && log_r == RB) {                                  \
+        if constexpr (TileKernel<R, NTB, RB>::LDS_BYTES <= 131072) {      \
+            launch_tile_inst<R, NTB, RB, MODE>(a, n_tiles, zparts, st);  \
+            return;                                                      \
+        }                                                                \
     }
 #define QS_TILE_ROW(NTB) \
     QS_TILE_CASE(NTB, 1) QS_TILE_CASE(NTB, 2) QS_TILE_CASE(NTB, 3) QS_TILE_CASE(NTB, 4) QS_TILE_CASE(NTB, 5)

@@ -47,7 +47,7 @@ EXPORTS = [
     "qs_batch_synchronize", "qs_batch_destroy", "qs_batch_plan",
     "qs_server_create", "qs_server_destroy", "qs_server_fits", "qs_server_admit", "qs_server_step_launch",
     "qs_server_step_wait", "qs_server_result", "qs_server_release", "qs_server_set_solo_tiles",
-    "qs_run_program_noalloc", "qs_compile_costed", "qs_run_circuit_costed",
+    "qs_run_program_noalloc", "qs_compile_costed", "qs_run_circuit_costed", "qs_run_circuit_expect_z",
 ]
 
 
@@ -152,6 +152,8 @@ def load() -> ctypes.CDLL:
     L.qs_run_circuit.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.POINTER(qs_run_opts)]
     L.qs_run_circuit_costed.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.POINTER(qs_run_opts),
                                         ctypes.POINTER(qs_pass_costs)]
+    L.qs_run_circuit_expect_z.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.POINTER(qs_run_opts),
+                                          ctypes.POINTER(qs_pass_costs), ctypes.POINTER(ctypes.c_double)]
     L.qs_read_amplitudes.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
     L.qs_read_state.argtypes = [_vp, _vp]
     L.qs_expect_z.argtypes = [_vp, _vp]
@@ -374,6 +376,16 @@ def qs_run_circuit_costed(h: int, gates, opts: qs_run_opts | None = None, costs:
     g = as_gates(gates)
     _chk(load().qs_run_circuit_costed(h, g.ctypes.data, len(g), ctypes.byref(opts) if opts is not None else None,
                                       ctypes.byref(costs) if costs is not None else None))
+
+
+def qs_run_circuit_expect_z(h: int, n: int, gates, opts: qs_run_opts | None = None,
+                            costs: qs_pass_costs | None = None) -> np.ndarray:
+    g = as_gates(gates)
+    out = np.zeros(n, dtype=np.float64)
+    _chk(load().qs_run_circuit_expect_z(h, g.ctypes.data, len(g), ctypes.byref(opts) if opts is not None else None,
+                                        ctypes.byref(costs) if costs is not None else None,
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
 
 
 def qs_read_amplitudes(h: int, idx) -> np.ndarray:
@@ -614,6 +626,10 @@ class State:
         else:
             qs_run_circuit_costed(self.h, gates, make_opts(**opts), costs)
         return self
+
+    def run_expect_z(self, gates, costs: qs_pass_costs | None = None, **opts) -> np.ndarray:
+        """run() and then expect_z(), the read-out folded into the last tile pass."""
+        return qs_run_circuit_expect_z(self.h, self.n, gates, make_opts(**opts), costs)
 
     def run_program(self, prog: "Program", noalloc: bool = False) -> "State":
         (qs_run_program_noalloc if noalloc else qs_run_program)(self.h, prog.h)
