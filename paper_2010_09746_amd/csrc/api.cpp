@@ -900,13 +900,14 @@ void fused_expect_z(qs_state *s, const Program &p, const TileOp *d_ops, size_t f
         const Launch &L = p.launches[lt];
         const int nv = 1 + L.log_r + L.log_nt;
         const uint64_t tiles = 1ull << (s->n - L.k);
-        ensure_work(s, (size_t)tiles * nv + (size_t)s->n + 1);
-        double *parts = s->d_work, *outd = s->d_work + (size_t)tiles * nv;
+        const size_t fw = zfold_work_doubles(tiles, s->n);
+        ensure_work(s, (size_t)tiles * nv + fw + (size_t)s->n + 1);
+        double *parts = s->d_work, *fwork = parts + (size_t)tiles * nv, *outd = fwork + fw;
         launch_range(s, p, from, lt, d_ops);
         launch_range(s, p, lt, lt + 1, d_ops, parts);
         launch_range(s, p, lt + 1, end, d_ops);
         timed(s->stream, P_ZFOLD, (double)tiles * nv * sizeof(double),
-              [&] { launch_zfold(parts, tiles, nv, s->n, m, outd, s->stream); });
+              [&] { launch_zfold(parts, tiles, nv, s->n, m, fwork, outd, s->stream); });
         hipchk(hipMemcpyAsync(r.data(), outd, (s->n + 1) * sizeof(double), hipMemcpyDeviceToHost, s->stream),
                "hipMemcpyAsync");
         hipchk(hipStreamSynchronize(s->stream), "hipStreamSynchronize");

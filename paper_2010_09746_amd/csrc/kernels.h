@@ -60,8 +60,9 @@ void launch_zsum(const void *state, qs_dtype dt, int n, double *work_dev, double
                  hipStream_t st);
 
 // The same sums from the per-tile read-out of a tile pass (zparts of
-// launch_tile_f32_z/f64_z, nv doubles per tile: T, then B_v for v = 1..nv-1,
-// the bits of the pass's store layout, slot bits first).  Output 1 + p sums,
+// launch_tile_f32_z/f64_z, nv values per tile, value v of tile t at
+// parts[v * tiles + t]: T, then B_v for v = 1..nv-1, the bits of the pass's
+// store layout, slot bits first).  Output 1 + p sums,
 // over tiles t, the probability that bit p is 1 where that bit is the XOR of
 // the layout bit v[p] (none when v[p] < 1) and of the bits of the tile index
 // in rm[p]: B_v or T - B_v by the parity of t & rm[p], or T or 0 without a
@@ -71,8 +72,10 @@ struct ZFoldMap {
     int32_t v[64];
     uint64_t rm[64];
 };
-void launch_zfold(const double *parts, uint64_t tiles, int nv, int n, const ZFoldMap &m, double *out_dev,
-                  hipStream_t st);
+// work_dev: zfold_work_doubles(tiles, n) doubles of partial sums
+size_t zfold_work_doubles(uint64_t tiles, int n);
+void launch_zfold(const double *parts, uint64_t tiles, int nv, int n, const ZFoldMap &m, double *work_dev,
+                  double *out_dev, hipStream_t st);
 
 // out_dev[2i], out_dev[2i+1] = amplitude at physical index idx_dev[i] (FP64).
 void launch_gather(const void *state, qs_dtype dt, const uint64_t *idx_dev, int64_t count,

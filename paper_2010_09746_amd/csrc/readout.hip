@@ -5,6 +5,8 @@
 // on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.cuh"
 #include "kernels.h"
 
@@ -106,22 +108,29 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double *part, uint64_t 
 
 // Fold the per-tile read-out of a tile pass into the sums of k_zsum (see
 // ZFoldMap): output 0 is the sum over tiles of T, output 1 + p that of the
-// probability of bit p.  Thread t of a block takes tiles t (mod 256) in order,
-// then the 256 sums are added in a fixed tree.
-__global__ __launch_bounds__(256) void k_zfold(const double *parts, uint64_t tiles, int nv, ZFoldMap m, double *out)
+// probability of bit p.  Block (s, o) takes slice s of the tiles for output
+// o: thread t of the block takes the slice's tiles t (mod 256) in order, the
+// 256 sums are added in a fixed tree into work[s * outs + o], and
+// k_sum_parts adds the slices in order.
+static uint64_t zfold_slices(uint64_t tiles) { return std::min<uint64_t>(256, std::max<uint64_t>(1, tiles >> 10)); }
+
+__global__ __launch_bounds__(256) void k_zfold(const double *parts, uint64_t tiles, uint64_t chunk, ZFoldMap m,
+                                               int outs, double *work)
 {
     __shared__ double red[256];
-    const int o = blockIdx.x;
+    const uint64_t s = blockIdx.x;
+    const int o = blockIdx.y;
     const int v = o == 0 ? 0 : m.v[o - 1];
     const uint64_t rm = o == 0 ? 0 : m.rm[o - 1];
+    const uint64_t t_end = std::min(tiles, (s + 1) * chunk);
     double r = 0.0;
-    for (uint64_t t = threadIdx.x; t < tiles; t += 256) {
-        const double T = parts[t * nv];
+    for (uint64_t t = s * chunk + threadIdx.x; t < t_end; t += 256) {
+        const double T = parts[t];
         const bool odd = (__popcll(t & rm) & 1) != 0;
         if (o == 0)
             r += T;
         else if (v >= 1)
-            r += odd ? T - parts[t * nv + v] : parts[t * nv + v];
+            r += odd ? T - parts[(uint64_t)v * tiles + t] : parts[(uint64_t)v * tiles + t];
         else if (odd)
             r += T;
     }
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(256) void k_zfold(const double *parts, uint64_t til
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        out[o] = red[0];
+        work[s * outs + o] = red[0];
 }
 
 template <typename R>
@@ -263,11 +272,18 @@ void launch_zsum(const void *state, qs_dtype dt, int n, double *work, double *ou
     check_launch("zsum final");
 }
 
-void launch_zfold(const double *parts, uint64_t tiles, int nv, int n, const ZFoldMap &m, double *out_dev,
-                  hipStream_t st)
+size_t zfold_work_doubles(uint64_t tiles, int n) { return (size_t)zfold_slices(tiles) * (size_t)(n + 1); }
+
+void launch_zfold(const double *parts, uint64_t tiles, int nv, int n, const ZFoldMap &m, double *work_dev,
+                  double *out_dev, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zfold, dim3(n + 1), dim3(256), 0, st, parts, tiles, nv, m, out_dev);
+    (void)nv;
+    const uint64_t S = zfold_slices(tiles), chunk = (tiles + S - 1) / S;
+    hipLaunchKernelGGL(k_zfold, dim3((unsigned)S, (unsigned)(n + 1)), dim3(256), 0, st, parts, tiles, chunk, m, n + 1,
+                       work_dev);
     check_launch("zfold");
+    hipLaunchKernelGGL(k_sum_parts, dim3(n + 1), dim3(256), 0, st, work_dev, S, n + 1, out_dev);
+    check_launch("zfold final");
 }
 
 void launch_gather(const void *state, qs_dtype dt, const uint64_t *idx, int64_t count, double *out, hipStream_t st)

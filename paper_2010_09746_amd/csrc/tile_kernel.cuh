@@ -599,16 +599,17 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     // from kernel arguments or from device memory.  With BASIS, a pass whose
     // TileArgs::io has bit 4 set reads nothing: its tiles start as the basis
     // state |0...0> (1 at physical index 0, 0 elsewhere).
-    // With ZB each tile also writes NV = 1 + LOG_R + LOG_NT doubles to
-    // zparts + NV t: the sum of |a|^2 over the tile, then for each register
-    // slot bit and each thread-id bit of the store layout (positions st_reg,
-    // st_lane) the sum of |a|^2 over the amplitudes whose bit there is 1,
-    // reduced in a fixed order (wavefront butterflies, then the wavefronts in
-    // order).
+    // With ZB each tile t also writes NV = 1 + LOG_R + LOG_NT doubles, value v
+    // at zparts[v * zstride + t]: the
+    // sum of |a|^2 over the tile, then for each register slot bit and each
+    // thread-id bit of the store layout (positions st_reg, st_lane) the sum of
+    // |a|^2 over the amplitudes whose bit there is 1, reduced in a fixed order
+    // (wavefront butterflies, then the wavefronts in order).
     static constexpr int NV = 1 + LOG_R + LOG_NT;
     template <bool PF, bool BASIS = false, bool ZB = false, typename A>
     static __device__ __forceinline__ void run_range(const A &a, unsigned char *lds, uint64_t t_first, uint64_t t_end,
-                                                     uint64_t t_step, Readout ro, double *zparts = nullptr)
+                                                     uint64_t t_step, Readout ro, double *zparts = nullptr,
+                                                     uint64_t zstride = 0)
     {
         C *st = reinterpret_cast<C *>(a.state);
         OpPtr ops = (OpPtr)(a.ops);
@@ -841,7 +842,7 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
             if (ro.out)
                 reduce_pair(nrm, z, ro.out + 2 * ((t - t_first) / t_step), reinterpret_cast<double *>(lds));
             if constexpr (ZB)
-                reduce_bits(zt, zu, direct ? fl : 0u, zparts + (uint64_t)NV * t, reinterpret_cast<double *>(lds));
+                reduce_bits(zt, zu, direct ? fl : 0u, zparts + t, zstride, reinterpret_cast<double *>(lds));
             lds_sync();  // the next tile reuses the LDS buffer
             if constexpr (PF) {
                 if (more) {
@@ -857,7 +858,7 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
     // >> q) is 1 (a slot whose exchange was applied by relabelling counts the
     // other half), thread bit i where the thread id has it.
     static __device__ __forceinline__ void reduce_bits(double zt, const double (&zu)[LOG_R], uint32_t flips,
-                                                       double *out, double *red)
+                                                       double *out, uint64_t stride, double *red)
     {
         const uint32_t tid = threadIdx.x;
         double zv[NV];
@@ -885,7 +886,7 @@ template <typename R, int LOG_NT, int LOG_R, bool HALF = true, bool STREAM = tru
             double r = 0.0;
             for (int w = 0; w < (NT >> 6); ++w)
                 r += red[w * NV + tid];
-            out[tid] = r;
+            out[stride * tid] = r;
         }
     }
 
@@ -945,8 +946,9 @@ __global__ __launch_bounds__(1 << LOG_NT) void k_tile_z(TileArgs a, double *zpar
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint64_t t = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    TileKernel<R, LOG_NT, LOG_R, true, STREAM>::template run_range<false, true, true>(a, lds_raw, t, t + 1, 1,
-                                                                                       {nullptr, 0}, zparts);
+    // value v of tile t at zparts[v * (tiles of the launch) + t]
+    TileKernel<R, LOG_NT, LOG_R, true, STREAM>::template run_range<false, true, true>(
+        a, lds_raw, t, t + 1, 1, {nullptr, 0}, zparts, (uint64_t)gridDim.x * gridDim.y);
 }
 
 template <typename R, int LOG_NT, int LOG_R, bool STREAM, bool ZB>
