@@ -319,14 +319,18 @@ qs_status qs_run_circuit_costed(qs_state *s, const qs_gate *gates, int64_t n_gat
 
 /* qs_run_circuit (costs NULL) or qs_run_circuit_costed, then <Z_q> of the
  * final state as qs_expect_z gives it (Section 2: measurement), with the
- * read-out folded into the last launch: when that launch is a tile pass it
- * also writes, per tile, the sum of |a|^2 and the sums over the amplitudes
- * whose bit is 1 at each of the tile's positions (FP64, fixed order), and a
- * small kernel folds them into the per-position sums, so no read-out pass
- * over the state runs; otherwise the read-out pass of qs_expect_z follows.
- * The last launch is enqueued once the program is complete.  expect_z: host,
- * n doubles (logical qubit order).  Same results as qs_run_circuit followed by
- * qs_expect_z, up to the order of the FP64 additions. */
+ * read-out folded into the last tile pass: each of its tiles also writes the
+ * sum of |a|^2 and the sums over the amplitudes whose bit is 1 at each of the
+ * tile's positions (FP64, fixed order), and a small kernel folds them into
+ * the per-position sums, so no read-out pass over the state runs.  CNOTs and
+ * CZs run on their own after that pass are allowed (a CZ changes no bit's
+ * probability, a CNOT makes its target bit the XOR of two bits; at most one
+ * tile bit per XOR); after any other launch, or a pass that does not move
+ * whole 128-byte lines, the read-out pass of qs_expect_z runs instead.  The
+ * last tile pass and the launches after it are enqueued once the program is
+ * complete.  expect_z: host, n doubles (logical qubit order).  Same results
+ * as qs_run_circuit followed by qs_expect_z, up to the order of the FP64
+ * additions. */
 qs_status qs_run_circuit_expect_z(qs_state *s, const qs_gate *gates, int64_t n_gates, const qs_run_opts *opts,
                                   const qs_pass_costs *costs, double *expect_z);
 
