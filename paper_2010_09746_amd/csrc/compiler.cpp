@@ -1039,7 +1039,56 @@ int schedule_segment(const std::vector<LGate> &lg, const qs_gate *g, const std::
 // on lane bits for whole 128-byte lines at load and store) whose next use in
 // a register set comes last; the other thread bits take the remaining tile
 // bits in ascending order.
-void assign_wave_bits(std::vector<TileOp> &ops, size_t begin, int k, int log_r, int log_nt, int low)
+// Lane order of the tile bits outside `taken`: the lowest `low` first (in
+// ascending order), then, up to bank_bits lanes, the lowest bit whose LDS bank
+// bits (the low bank_bits bits of lds_swizzle of the bit) are independent over
+// GF(2) of those of the lanes already placed, so that the lanes one LDS access
+// serves together (2^bank_bits of them: 128 bytes of elements) hit distinct
+// banks wherever the free bits allow; the rest in ascending order.
+std::vector<int> bank_lane_order(int k, uint32_t taken, int low, int bank_bits)
+{
+    std::vector<int> order;
+    std::vector<char> used(k, 0);
+    uint32_t basis[8] = {};  // XOR basis of the placed lanes' bank bits, by leading bit
+    auto reduces_to_zero = [&](int b) {
+        uint32_t v = lds_swizzle(1u << b, k) & ((1u << bank_bits) - 1u);
+        for (int t = bank_bits - 1; t >= 0 && v; --t)
+            if ((v >> t) & 1u)
+                v = basis[t] ? v ^ basis[t] : v;
+        return v == 0;
+    };
+    auto insert = [&](int b) {
+        uint32_t v = lds_swizzle(1u << b, k) & ((1u << bank_bits) - 1u);
+        for (int t = bank_bits - 1; t >= 0 && v; --t)
+            if ((v >> t) & 1u) {
+                if (!basis[t]) {
+                    basis[t] = v;
+                    break;
+                }
+                v ^= basis[t];
+            }
+        order.push_back(b);
+        used[b] = 1;
+    };
+    for (int b = 0; b < low && b < k; ++b)
+        if (!((taken >> b) & 1u))
+            insert(b);
+    while ((int)order.size() < bank_bits) {
+        int pick = -1;
+        for (int b = 0; b < k && pick < 0; ++b)
+            if (!used[b] && !((taken >> b) & 1u) && !reduces_to_zero(b))
+                pick = b;
+        if (pick < 0)
+            break;
+        insert(pick);
+    }
+    for (int b = 0; b < k; ++b)
+        if (!used[b] && !((taken >> b) & 1u))
+            order.push_back(b);
+    return order;
+}
+
+void assign_wave_bits(std::vector<TileOp> &ops, size_t begin, int k, int log_r, int log_nt, int low, int bank_bits)
 {
     const int nw = log_nt - 6;
     if (nw <= 0)
@@ -1082,14 +1131,15 @@ void assign_wave_bits(std::vector<TileOp> &ops, size_t begin, int k, int log_r, 
             for (int i = 0; i < nw; ++i)
                 W |= 1u << cand[i].second;
         }
-        uint64_t lanes = 0;
-        int i = 0;
-        for (int b = 0; b < k; ++b)
-            if (!((sets[j] >> b) & 1u) && !((W >> b) & 1u))
-                lanes |= (uint64_t)b << (4 * i++);
+        // lanes: the lowest `low` tile bits first, then bits that give the
+        // lanes one LDS access serves together distinct banks, then the rest
+        std::vector<int> order = bank_lane_order(k, sets[j] | W, low, bank_bits);
         for (int b = 0; b < k; ++b)
             if ((W >> b) & 1u)
-                lanes |= (uint64_t)b << (4 * i++);
+                order.push_back(b);
+        uint64_t lanes = 0;
+        for (size_t i = 0; i < order.size(); ++i)
+            lanes |= (uint64_t)order[i] << (4 * i);
         op.hbit = lanes;
         op.aux = keep ? REMAP_WAVE_LOCAL : 0u;
     }
@@ -1439,7 +1489,8 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
                     p.stats.n_remaps += schedule_segment(lg, g, gi, k, log_r, p.ops, pf, lane_bits, lane_eager);
                     // lane gates name thread bits of the ascending map
                     if (lane_bits == 0)
-                        assign_wave_bits(p.ops, (size_t)L.op_begin, k, log_r, log_nt, direct_low_bits(dt));
+                        assign_wave_bits(p.ops, (size_t)L.op_begin, k, log_r, log_nt, direct_low_bits(dt),
+                                         dt == QS_C64 ? 5 : 4);
                     L.op_count = (int)p.ops.size() - L.op_begin;
                     append_store_lane_swaps(L, p.ops, dt);
                     set_direct_io(L, p.ops, dt);
