@@ -1106,7 +1106,9 @@ void assign_wave_bits(std::vector<TileOp> &ops, size_t begin, int k, int log_r, 
         TileOp &op = ops[rl[j]];
         const bool keep = j > 0 && W != 0 && (sets[j] & W) == 0;
         if (!keep) {
-            // candidates by next use (never: past the end), higher bits first on ties
+            // candidates by next use (never: past the end); on ties bits with no
+            // LDS bank bits first (they cannot spread a lane access over banks),
+            // then higher bits
             std::vector<std::pair<size_t, int>> cand;
             for (int b = k - 1; b >= low; --b) {
                 if ((sets[j] >> b) & 1u)
@@ -1123,9 +1125,12 @@ void assign_wave_bits(std::vector<TileOp> &ops, size_t begin, int k, int log_r, 
                 W = 0;  // keep the ascending map
                 continue;
             }
+            auto no_bank = [&](int b) { return (lds_swizzle(1u << b, k) & ((1u << bank_bits) - 1u)) == 0; };
             std::stable_sort(cand.begin(), cand.end(),
-                             [](const std::pair<size_t, int> &a, const std::pair<size_t, int> &b) {
-                                 return a.first > b.first;
+                             [&](const std::pair<size_t, int> &a, const std::pair<size_t, int> &b) {
+                                 if (a.first != b.first)
+                                     return a.first > b.first;
+                                 return no_bank(a.second) && !no_bank(b.second);
                              });
             W = 0;
             for (int i = 0; i < nw; ++i)
