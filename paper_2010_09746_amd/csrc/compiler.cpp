@@ -277,16 +277,19 @@ PassRunner::~PassRunner() { delete ps_; }
 bool PassRunner::step(std::vector<Instr> &out)
 {
     PassState &ps = *ps_;
-    if (ps.remaining() == 0)
-        return false;
+    if (!swept_) {
+        if (ps.remaining() == 0)
+            return false;
+        emitted_.clear();
+        ps.sweep(sigma_.data(), emitted_);
+        for (int v : emitted_)
+            out.push_back(Instr{0, v, {}});
+        stats_.n_apply += (int64_t)emitted_.size();
+        swept_ = true;
+        return ps.remaining() != 0;
+    }
+    swept_ = false;
     const int n = n_, m = m_;
-    emitted_.clear();
-    ps.sweep(sigma_.data(), emitted_);
-    for (int v : emitted_)
-        out.push_back(Instr{0, v, {}});
-    stats_.n_apply += (int64_t)emitted_.size();
-    if (ps.remaining() == 0)
-        return false;
 
     // the chain of Algorithm 1's exchanges (each strictly raising the count),
     // with the placement and count after each link
@@ -1511,7 +1514,9 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         bool more = true;
         while (more) {
             more = pr.step(p.instrs);
-            lower(!more);
+            // a closed run of ApplyGate instructions is lowered (and may be
+            // launched) before the PermuteQubits after it is chosen
+            lower(!more || pr.run_closed());
             if (progress)
                 progress(p);
         }

@@ -140,7 +140,13 @@ public:
     ~PassRunner();
     PassRunner(const PassRunner &) = delete;
     PassRunner &operator=(const PassRunner &) = delete;
+    // One half of an iteration of Algorithm 1 per call: first the ApplyGate
+    // instructions of every gate that is ready and local, then the
+    // PermuteQubits (or the fallback gate).  False when the circuit is done.
     bool step(std::vector<Instr> &out);
+    // after the first half: the run of ApplyGate instructions just emitted is
+    // complete (a PermuteQubits, a fallback gate or the end follows)
+    bool run_closed() const { return swept_; }
     const PassStats &stats() const { return stats_; }
     const std::vector<GateInfo> &gate_info() const { return gi_; }
 
@@ -153,6 +159,7 @@ private:
     PassState *ps_ = nullptr;
     std::vector<int> sigma_, emitted_;
     PassStats stats_;
+    bool swept_ = false;
 };
 
 struct Program {
