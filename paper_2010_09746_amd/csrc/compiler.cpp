@@ -113,23 +113,46 @@ Dag build_dag(const qs_gate *g, const std::vector<GateInfo> &gi, int n)
     d.pred.resize(ng);
     d.succ.resize(ng);
     std::vector<std::vector<int>> uses(n);
+    // cut[q]: every gate on q before uses[q][cut[q]] is an ancestor of that
+    // gate, so a gate that depends on it needs no edge from them (the edges
+    // left out are implied, readiness is unchanged)
+    std::vector<size_t> cut(n, 0);
     std::vector<int> seen(ng, -1);
     for (int v = 0; v < ng; ++v) {
         const int qs[2] = {gi[v].q0, gi[v].q1};
+        bool all_pred[2] = {true, true};
         for (int k = 0; k < gi[v].nq; ++k) {
-            for (int h : uses[qs[k]]) {
-                if (seen[h] == v)
+            const std::vector<int> &u = uses[qs[k]];
+            // the cut gate commuting with v (an identical gate) implies nothing
+            size_t lo = cut[qs[k]];
+            if (lo < u.size() && gates_commute(g[u[lo]], gi[u[lo]], g[v], gi[v]))
+                lo = 0;
+            for (size_t i = lo; i < u.size(); ++i) {
+                const int h = u[i];
+                if (seen[h] == v) {
+                    all_pred[k] = all_pred[k] && !d.pred[v].empty() &&
+                                  std::find(d.pred[v].begin(), d.pred[v].end(), h) != d.pred[v].end();
                     continue;
+                }
                 seen[h] = v;
                 if (!gates_commute(g[h], gi[h], g[v], gi[v]))
                     d.pred[v].push_back(h);
+                else
+                    all_pred[k] = false;
             }
+            all_pred[k] = all_pred[k] && lo == cut[qs[k]];
         }
         std::sort(d.pred[v].begin(), d.pred[v].end());
         for (int h : d.pred[v])
             d.succ[h].push_back(v);
-        for (int k = 0; k < gi[v].nq; ++k)
-            uses[qs[k]].push_back(v);
+        for (int k = 0; k < gi[v].nq; ++k) {
+            const int q = qs[k];
+            // v acts on q with a general matrix and depends on every gate on q
+            // from the cut on: every earlier gate on q is now its ancestor
+            if (act_on(gi[v], q) == ACT_G && all_pred[k])
+                cut[q] = uses[q].size();
+            uses[q].push_back(v);
+        }
     }
     return d;
 }
