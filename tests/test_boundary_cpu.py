@@ -11,7 +11,7 @@ import pytest
 import oracle as O
 from paper_2010_09746_amd import qsim as Q
 from workloads import (config_circuit, layered_circuit, make_gates, mixed_circuit, paper_random_circuit,
-                       qft_like_circuit, KIND_CX, KIND_U, H)
+                       qft_like_circuit, haar_u2, KIND_CU, KIND_CX, KIND_CZ, KIND_U, H)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -85,6 +85,32 @@ def test_pass_matches_oracle_all_gate_kinds(n, m, seed):
 @pytest.mark.parametrize("r,pinned", [(2, 0), (4, 3), (8, 3), (1, 3)])
 def test_pass_extensions_match_oracle(r, pinned):
     _same_as_oracle(layered_circuit(16, 12, seed=9), 16, 10, r=r, pinned=pinned)
+
+
+@pytest.mark.parametrize("m,r,pinned,seed", [(5, 1, 0, 1), (6, 4, 2, 2), (7, 8, 3, 3)])
+def test_pass_matches_oracle_repeated_gates(m, r, pinned, seed):
+    """Gates from a small alphabet (a Haar U(2), H, X, a diagonal, CX, CZ, a
+    controlled Haar U(2)) repeat often, so identical gates (which commute)
+    follow each other on a qubit: the dependency graph may leave out an edge
+    only where another path implies it."""
+    n = 10
+    rng = np.random.default_rng(seed)
+    u = [haar_u2(rng) for _ in range(2)]
+    one = [u[0], H, np.array([[0, 1], [1, 0]], dtype=complex), np.diag([1.0, np.exp(0.7j)])]
+    recs = []
+    for _ in range(400):
+        a = int(rng.integers(0, 7))
+        q = int(rng.integers(0, 3 if a % 2 else n))  # crowd a few qubits
+        t = int((q + 1 + rng.integers(0, n - 1)) % n)
+        if a < 4:
+            recs.append((KIND_U, q, -1, one[a]))
+        elif a == 4:
+            recs.append((KIND_CX, q, t, None))
+        elif a == 5:
+            recs.append((KIND_CZ, q, t, None))
+        else:
+            recs.append((KIND_CU, q, t, u[1]))
+    _same_as_oracle(make_gates(recs), n, m, r=r, pinned=pinned)
 
 
 def test_pass_matches_oracle_layered_config_shape():
