@@ -52,7 +52,7 @@ typedef enum {
     QS_ERR_OOM = -2,         /* device allocation failed */
     QS_ERR_BUDGET = -3,      /* a request does not fit the memory budget */
     QS_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed */
-    QS_ERR_UNSUPPORTED = -5, /* valid request outside what this build implements */
+    QS_ERR_UNSUPPORTED = -5, /* valid request outside what the library implements */
     QS_ERR_STATE = -6        /* handle in the wrong state (e.g. program compiled for another placement) */
 } qs_status;
 
