@@ -556,7 +556,8 @@ LGate lower_gate(const qs_gate &g, const GateInfo &gi, const std::vector<int> &s
 // [1/16, 16], the scalar's magnitude [2^-8, 2^8], or |p|, |q| exceed 16,
 // so that complex64 states keep at least 2^-(2n+8) of their magnitude range.
 //
-// a I + b X pending factors are used for complex128 states only.  A diagonal
+// a I + b X pending factors are used for complex128 states only, and for
+// complex64 states with QS_OPT_X_FACTORS.  A diagonal
 // pending factor scales each stored amplitude, so rounding errors stay
 // relative to each amplitude; a I + b X mixes the two amplitudes of a pair,
 // and with many qubits holding one at once the stored state is their tensor
@@ -1356,7 +1357,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
     p.n = n;
     p.dt = dt;
     if (o.flags & ~(QS_OPT_FULL_MATRICES | QS_OPT_LANE_GATES | QS_OPT_LANE_GATES_WIDE | QS_OPT_LANE_EAGER |
-                    QS_OPT_FROM_ZERO))
+                    QS_OPT_FROM_ZERO | QS_OPT_X_FACTORS))
         fail(QS_ERR_ARG, "unknown flags");
     p.opts = o;
     p.sigma0.resize(n);
@@ -1450,7 +1451,7 @@ void compile_program(const qs_gate *g, int64_t ng, int n, qs_dtype dt, const int
         // reduced one-qubit updates only where tile passes run them
         pf.on = tiled && (o.flags & QS_OPT_FULL_MATRICES) == 0;
         if (pf.on)
-            pf.init(g, gi, ng, n, dt == QS_C128);
+            pf.init(g, gi, ng, n, dt == QS_C128 || (o.flags & QS_OPT_X_FACTORS) != 0);
         const int lane_bits = (o.flags & QS_OPT_LANE_GATES_WIDE) ? 4 : (o.flags & QS_OPT_LANE_GATES) ? 2 : 0;
         const bool lane_eager = (o.flags & QS_OPT_LANE_EAGER) != 0;
         // Lower the instructions from i on.  A run of ApplyGate instructions is

@@ -225,10 +225,12 @@ QS_OPT_LANE_GATES = 2
 QS_OPT_LANE_GATES_WIDE = 4
 QS_OPT_LANE_EAGER = 8
 QS_OPT_FROM_ZERO = 16
+QS_OPT_X_FACTORS = 32
 
 
 def make_opts(form="pass", k_tile=12, max_swaps=1, pinned=0, perm_exec="move", max_fuse=0,
-              reg_bits=0, full_matrices=False, lane_gates=0, lane_eager=False, from_zero=False) -> qs_run_opts:
+              reg_bits=0, full_matrices=False, lane_gates=0, lane_eager=False, from_zero=False,
+              x_factors=False) -> qs_run_opts:
     o = qs_run_opts()
     o.form = {"plain": QS_FORM_PLAIN, "pass": QS_FORM_PASS}.get(form, form)
     o.k_tile = k_tile
@@ -242,7 +244,8 @@ def make_opts(form="pass", k_tile=12, max_swaps=1, pinned=0, perm_exec="move", m
     o.flags = ((QS_OPT_FULL_MATRICES if full_matrices else 0)
                | {0: 0, 2: QS_OPT_LANE_GATES, 4: QS_OPT_LANE_GATES_WIDE}[lane_gates]
                | (QS_OPT_LANE_EAGER if lane_eager else 0)
-               | (QS_OPT_FROM_ZERO if from_zero else 0))
+               | (QS_OPT_FROM_ZERO if from_zero else 0)
+               | (QS_OPT_X_FACTORS if x_factors else 0))
     return o
 
 

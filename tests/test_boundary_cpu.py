@@ -245,7 +245,7 @@ def test_lane_gate_options():
     with pytest.raises(ValueError):
         Q.make_opts(lane_gates=3)
     o = Q.make_opts(**base)
-    o.flags = 32
+    o.flags = 64
     with pytest.raises(Q.QsimError):
         Q.qs_compile(g[:10], 30, "c128", None, o)
 

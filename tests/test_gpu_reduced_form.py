@@ -142,6 +142,28 @@ def test_pending_factor_commuting_with_cnot_targets(dt):
         assert 1 - fid <= 1e-6
 
 
+def test_complex64_x_factors_on_request():
+    """complex64 with QS_OPT_X_FACTORS keeps a I + b X factors: no phase
+    operation before CNOT targets, within the complex64 bounds against the
+    oracle (its rounding errors are larger than with diagonal factors)."""
+    n = 16
+    _say("complex64 with a I + b X factors")
+    g = layered_circuit(n, 20, seed=13)
+    opts = dict(form="pass", k_tile=11, max_swaps=8, pinned=4, perm_exec="relabel")
+    P = Q.Program(g, n, "c64", **opts)
+    diag_only = P.op_counts()
+    P.close()
+    P = Q.Program(g, n, "c64", x_factors=True, **opts)
+    with_x = P.op_counts()
+    P.close()
+    assert diag_only["phase"] > 0 and with_x["phase"] < diag_only["phase"] / 4
+    ref = O.run(g, n)
+    got = _run(g, n, "c64", x_factors=True, **opts)
+    assert np.abs(got - ref).max() <= TOL["c64"]
+    fid = abs(np.vdot(ref, got)) ** 2 / np.vdot(got, got).real
+    assert 1 - fid <= 1e-6
+
+
 @pytest.mark.parametrize("r,pinned", [(0, 0), (2, 9)])
 def test_launches_of_their_own_settle_phases(r, pinned):
     """r = 0 (fusion without the pass) and pinned = k (no exchange allowed, so
